@@ -1,0 +1,292 @@
+// C ABI of libmandel.so: argument checks, workspaces and launches.
+// The operation and every argument are specified in include/mandel.h.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <utility>
+
+#include "mandel.h"
+#include "mandel_internal.h"
+#include "render_kernels.h"
+
+namespace mandel {
+
+static thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what)
+{
+    return fail(MANDEL_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+void clear_error() { g_err.clear(); }
+
+// ---- per (device, stream) workspace ----------------------------------------
+namespace {
+struct Workspace {
+    unsigned long long *head = nullptr;
+};
+std::mutex g_ws_mu;
+std::map<std::pair<int, hipStream_t>, Workspace> g_ws;
+} // namespace
+
+int workspace_head(hipStream_t s, unsigned long long **head)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return hip_fail(e, "hipGetDevice");
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    Workspace &w = g_ws[{dev, s}];
+    if (!w.head) {
+        e = hipMalloc((void **)&w.head, 256);
+        if (e != hipSuccess) {
+            w.head = nullptr;
+            return fail(MANDEL_ENOMEM, "hipMalloc(workspace): %s", hipGetErrorString(e));
+        }
+    }
+    *head = w.head;
+    return MANDEL_OK;
+}
+
+int device_cus(int *cus)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return hip_fail(e, "hipGetDevice");
+    e = hipDeviceGetAttribute(cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess)
+        return hip_fail(e, "hipDeviceGetAttribute");
+    return MANDEL_OK;
+}
+
+// ---- argument checks ----------------------------------------------------------
+int64_t tile_count(int32_t m, int32_t n, int32_t tw, int32_t th)
+{
+    if (m <= 0 || n <= 0 || tw <= 0 || th <= 0)
+        return 0;
+    return (int64_t)((m + th - 1) / th) * (int64_t)((n + tw - 1) / tw);
+}
+
+// Fills d (all but out_off and tile_off) from one view's arguments.
+int make_view(const mandel_window *w, int32_t m, int32_t n, int32_t max_iter, double R,
+              int32_t tile_w, int32_t tile_h, ViewDesc *d)
+{
+    if (!w)
+        return fail(MANDEL_EINVAL, "window is NULL");
+    if (m < 0 || n < 0)
+        return fail(MANDEL_EINVAL, "negative size m=%d n=%d", m, n);
+    if ((int64_t)m * (int64_t)n >= (int64_t(1) << 40))
+        return fail(MANDEL_EINVAL, "image too large: %d x %d", m, n);
+    if (max_iter < 1 || max_iter > (1 << 30))
+        return fail(MANDEL_EINVAL, "max_iter=%d outside [1, 2^30]", max_iter);
+    if (!std::isfinite(R) || !(R > 0.0) || R > 1e150)
+        return fail(MANDEL_EINVAL, "escape radius R=%g outside (0, 1e150]", R);
+    if (!std::isfinite(w->cx0) || !std::isfinite(w->cy0) || !std::isfinite(w->dx) ||
+        !std::isfinite(w->dy))
+        return fail(MANDEL_EINVAL, "window has a non-finite value");
+    if (!(w->dx > 0.0) || !(w->dy > 0.0))
+        return fail(MANDEL_EINVAL, "pixel pitch must be > 0 (dx=%g dy=%g)", w->dx, w->dy);
+    // Corner points (extreme offsets); c is monotone in the offset.
+    const double ox = 0.5 - 0.5 * (double)n, oy = 0.5 - 0.5 * (double)m;
+    const double c0x = w->cx0 + ox * w->dx, c1x = w->cx0 - ox * w->dx;
+    const double c0y = w->cy0 + oy * w->dy, c1y = w->cy0 - oy * w->dy;
+    if (m > 0 && n > 0 &&
+        (!std::isfinite(c0x) || !std::isfinite(c1x) || !std::isfinite(c0y) ||
+         !std::isfinite(c1y)))
+        return fail(MANDEL_EINVAL, "window corners are not finite");
+    std::memset(d, 0, sizeof *d);
+    d->cx0 = w->cx0;
+    d->cy0 = w->cy0;
+    d->dx = w->dx;
+    d->dy = w->dy;
+    d->R2 = R * R;
+    // Deferred tests are exact when R >= 2 and |c| <= (R^2 - R)(1 - 2^-20): after the
+    // first |z|^2 > R^2 the modulus then grows at every update, up to overflow to
+    // inf/NaN, which stays non-finite.  The bound is taken with a 2^-19 margin so that
+    // rounding in the device's |c|^2 cannot cross it.
+    if (R >= 2.0) {
+        const double b = (R * R - R) * (1.0 - 0x1p-19);
+        d->safe2 = b * b;
+    } else {
+        d->safe2 = -1.0;
+    }
+    d->m = m;
+    d->n = n;
+    d->max_iter = max_iter;
+    d->tiles_x = (n + tile_w - 1) / tile_w;
+    d->tiles_y = (m + tile_h - 1) / tile_h;
+    return MANDEL_OK;
+}
+
+int check_sched(const mandel_sched *s, mandel_sched *o)
+{
+    mandel_sched d;
+    std::memset(&d, 0, sizeof d);
+    if (s)
+        d = *s;
+    if (d.policy < MANDEL_FCFS_TILES || d.policy > MANDEL_GRID_TILES)
+        return fail(MANDEL_EINVAL, "unknown policy %d", d.policy);
+    if (d.tile_w == 0)
+        d.tile_w = 64;
+    if (d.tile_h == 0)
+        d.tile_h = 8;
+    if (d.tile_w < 1 || d.tile_h < 1 || (int64_t)d.tile_w * d.tile_h > (1 << 20))
+        return fail(MANDEL_EINVAL, "bad tile shape %d x %d", d.tile_w, d.tile_h);
+    if (d.grain == 0)
+        d.grain = 1;
+    if (d.grain < 1 || d.grain > (1 << 20))
+        return fail(MANDEL_EINVAL, "bad grain %d", d.grain);
+    if (d.waves_per_group == 0)
+        d.waves_per_group = 4;
+    if (d.waves_per_group < 1 || d.waves_per_group > 16)
+        return fail(MANDEL_EINVAL, "waves_per_group=%d outside [1, 16]", d.waves_per_group);
+    if (d.workers < 0)
+        return fail(MANDEL_EINVAL, "negative workers");
+    if ((d.policy == MANDEL_STATIC_ROWS || d.policy == MANDEL_ALTERNATING_ROWS) && d.workers < 1)
+        return fail(MANDEL_EINVAL, "row policies need workers >= 1");
+    if (d.check_every != 0 && d.check_every != 1)
+        return fail(MANDEL_EINVAL, "check_every must be 0 or 1");
+    if (d.block_iters == 0)
+        d.block_iters = 32;
+    if (d.block_iters < 1 || d.block_iters > 1024)
+        return fail(MANDEL_EINVAL, "block_iters=%d outside [1, 1024]", d.block_iters);
+    if (d.young_iters == 0)
+        d.young_iters = 16;
+    if (d.young_iters < 0)
+        return fail(MANDEL_EINVAL, "negative young_iters");
+    if (d.policy == MANDEL_ORDERED_TILES && !d.order)
+        return fail(MANDEL_EINVAL, "ORDERED_TILES needs an order array");
+    *o = d;
+    return MANDEL_OK;
+}
+
+// Launch geometry for a tile policy: persistent groups or one group per tile.
+int tile_grid(const mandel_sched &s, bool batch, int64_t ntiles, dim3 *grid, dim3 *block)
+{
+    if (s.policy == MANDEL_GRID_TILES) {
+        if (ntiles > (int64_t)1 << 26)
+            return fail(MANDEL_EINVAL, "GRID_TILES launch limited to 2^26 tiles");
+        unsigned gx = (unsigned)(ntiles < 65535 ? ntiles : 65535);
+        unsigned gy = (unsigned)((ntiles + gx - 1) / gx);
+        *grid = dim3(gx, gy);
+        *block = dim3(64);
+        return MANDEL_OK;
+    }
+    const int threads = 64 * s.waves_per_group;
+    int groups = s.workers;
+    if (groups == 0) {
+        int cus = 0;
+        int rc = device_cus(&cus);
+        if (rc)
+            return rc;
+        const bool defer = s.check_every == 0;
+        groups = cus * persistent_blocks_per_cu(s.policy, batch, defer, threads);
+    }
+    *grid = dim3((unsigned)groups);
+    *block = dim3((unsigned)threads);
+    return MANDEL_OK;
+}
+
+} // namespace mandel
+
+using namespace mandel;
+
+extern "C" {
+
+const char *mandel_last_error(void) { return g_err.c_str(); }
+
+const char *mandel_version(void) { return "mandel-gfx950 0.1"; }
+
+int64_t mandel_tile_count(int32_t m, int32_t n, int32_t tile_w, int32_t tile_h)
+{
+    return tile_count(m, n, tile_w, tile_h);
+}
+
+int mandel_render_sched(const mandel_window *w, int32_t m, int32_t n, int32_t max_iter,
+                        double R, int32_t *out, const mandel_sched *sp, void *stream)
+{
+    clear_error();
+    mandel_sched s;
+    int rc = check_sched(sp, &s);
+    if (rc)
+        return rc;
+    ViewDesc v;
+    rc = make_view(w, m, n, max_iter, R, s.tile_w, s.tile_h, &v);
+    if (rc)
+        return rc;
+    if (m == 0 || n == 0)
+        return MANDEL_OK;
+    if (!out)
+        return fail(MANDEL_EINVAL, "out is NULL");
+    hipStream_t st = (hipStream_t)stream;
+    const bool rows = s.policy == MANDEL_STATIC_ROWS || s.policy == MANDEL_ALTERNATING_ROWS;
+    const int64_t ntiles = rows ? (int64_t)m : tile_count(m, n, s.tile_w, s.tile_h);
+
+    RenderArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.v0 = v;
+    a.v0.out_off = 0;
+    a.v0.tile_off = 0;
+    a.views = nullptr;
+    a.nviews = 1;
+    a.tile_w = s.tile_w;
+    a.tile_h = s.tile_h;
+    a.grain = s.grain;
+    a.ntiles = ntiles;
+    a.block_iters = s.block_iters;
+    a.young_iters = s.young_iters;
+    a.out = out;
+    a.order = s.order;
+    a.tile_cost = rows ? nullptr : s.tile_cost;
+    a.claims = rows ? nullptr : s.claims;
+    a.stats = s.stats;
+
+    unsigned long long *head = nullptr;
+    rc = workspace_head(st, &head);
+    if (rc)
+        return rc;
+    a.head = head;
+
+    dim3 grid, block;
+    if (rows) {
+        grid = dim3((unsigned)s.workers);
+        block = dim3((unsigned)(64 * s.waves_per_group));
+    } else {
+        rc = tile_grid(s, false, ntiles, &grid, &block);
+        if (rc)
+            return rc;
+    }
+    hipError_t e = launch_clear(head, a.tile_cost, a.claims, a.tile_cost || a.claims ? ntiles : 0, st);
+    if (e != hipSuccess)
+        return hip_fail(e, "clear launch");
+    e = launch_render(a, s.policy, false, s.check_every == 0, grid, block, st);
+    if (e != hipSuccess)
+        return hip_fail(e, "render launch");
+    return MANDEL_OK;
+}
+
+int mandel_render(const mandel_window *w, int32_t m, int32_t n, int32_t max_iter, double R,
+                  int32_t *out, void *stream)
+{
+    return mandel_render_sched(w, m, n, max_iter, R, out, nullptr, stream);
+}
+
+} // extern "C"

@@ -1,0 +1,53 @@
+// Shared host/device declarations of the render kernel family.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mandel {
+
+enum : int {
+    POLICY_FCFS_TILES = 0,
+    POLICY_STATIC_ROWS = 1,
+    POLICY_ALTERNATING_ROWS = 2,
+    POLICY_ORDERED_TILES = 3,
+    POLICY_GRID_TILES = 4,
+};
+
+// One view as the kernels see it (96 bytes).
+struct ViewDesc {
+    double cx0, cy0, dx, dy; // window: centre and pixel pitch
+    double R2;               // R*R, rounded once
+    double safe2;            // |c|^2 bound below which the deferred test is exact (<0: never)
+    int64_t out_off;         // element offset of this view's image in the output buffer
+    int64_t tile_off;        // global id of this view's first tile
+    int32_t m, n;            // rows, columns
+    int32_t max_iter;
+    int32_t tiles_x;         // tiles per tile-row
+    int32_t tiles_y;
+    int32_t pad[3];
+};
+static_assert(sizeof(ViewDesc) == 96, "ViewDesc layout");
+
+struct RenderArgs {
+    ViewDesc v0;                   // the view when there is only one
+    const ViewDesc *views;         // batch: device table, ascending tile_off
+    int32_t nviews;
+    int32_t tile_w, tile_h, grain;
+    int64_t ntiles;
+    int32_t block_iters;           // K: updates per deferred block
+    int32_t young_iters;           // P: pixels younger than P updates are tested every update
+    int32_t *out;                  // output base
+    unsigned long long *head;      // queue head (FCFS / ORDERED)
+    const int32_t *order;          // ORDERED: queue slot -> tile id
+    int64_t *tile_cost;            // optional: sum of counts per tile
+    int32_t *claims;               // optional: claims per tile
+    uint64_t *stats;               // optional: [wave iterations, sum counts, waves, items]
+};
+
+hipError_t launch_render(const RenderArgs &a, int policy, bool batch, bool defer, dim3 grid,
+                         dim3 block, hipStream_t s);
+hipError_t launch_clear(unsigned long long *head, int64_t *tile_cost, int32_t *claims,
+                        int64_t ntiles, hipStream_t s);
+int persistent_blocks_per_cu(int policy, bool batch, bool defer, int threads);
+
+} // namespace mandel

@@ -1,0 +1,490 @@
+// Escape-time render kernels for gfx950 (CDNA4, wave64).
+//
+// The method is the paper's Boolean escape-time generation (Sec. I, Eq. (1)
+// and Eq. (2)); its load-imbalance problem (Sec. III: the middle rows cost far
+// more than the top and bottom) is handled here inside one GPU:
+//
+//   * every wavefront is a worker; it pulls work items (tiles or rows) from a
+//     source chosen by the policy -- a device-wide atomic queue (the analogue
+//     of Sec. III-B), a permuted queue, the contiguous row blocks of Sec. III-A
+//     or the alternating rows of Sec. III-C;
+//   * a lane that finishes its pixel takes the next pixel of the wave's
+//     current item at once (ballot + mbcnt compaction), and the wave claims
+//     the next item as soon as the current one has no pixels left, so lanes
+//     idle only in the very last item of the whole launch;
+//   * the |z|^2 > R^2 test may be deferred over blocks of K updates for
+//     pixels where an escape provably cannot be undone (see safe2 below);
+//     a lane found escaped at the end of a block rewinds to its snapshot and
+//     replays the block with a test after every update, so the count is exact.
+//
+// Arithmetic contract (must match the CPU definition bit for bit): IEEE
+// binary64, round to nearest even, one rounding per operation, in the order
+//     x' = (x*x - y*y) + cx,   y' = 2*(x*y) + cy
+// The file is compiled with -ffp-contract=off.  The only fused operation is
+// the deliberate fma(2, x*y, cy): multiplying the rounded product by 2 is
+// exact, so fma rounds once exactly where 2*(x*y) + cy rounds once.  (It would
+// differ only if 2*(x*y) overflowed; before the escape |x|, |y| are bounded by
+// about R <= 1e150, so it cannot.)
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "render_kernels.h"
+
+#pragma clang fp contract(off)
+
+namespace mandel {
+
+namespace {
+
+__device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
+
+// Bit l set iff lane l is active and p holds there (one SGPR pair, no VALU copy).
+__device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
+
+__device__ __forceinline__ uint32_t rank_in(uint64_t mask)
+{
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+__device__ __forceinline__ int32_t bcast_i32(int32_t v)
+{
+    return __builtin_amdgcn_readfirstlane(v);
+}
+
+__device__ __forceinline__ int64_t bcast_i64(int64_t v)
+{
+    uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)(uint64_t)v);
+    uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)v >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t v)
+{
+    for (int off = 32; off >= 1; off >>= 1) {
+        uint32_t o = (uint32_t)__shfl_xor((int)v, off, 64);
+        v = v < o ? v : o;
+    }
+    return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
+}
+
+__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v)
+{
+    for (int off = 32; off >= 1; off >>= 1) {
+        uint64_t o = (uint64_t)__shfl_xor((long long)v, off, 64);
+        v += o;
+    }
+    return v;
+}
+
+// Tile id -> view index in a batch: the views hold ascending first-tile ids.
+__device__ __forceinline__ int32_t find_view(const ViewDesc *views, int32_t nviews, int64_t t)
+{
+    int32_t lo = 0, hi = nviews - 1;
+    while (lo < hi) {
+        int32_t mid = (lo + hi + 1) >> 1;
+        if (views[mid].tile_off <= t)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+} // namespace
+
+// Clears the queue head and the optional per-tile logs before a launch.
+__global__ void clear_kernel(unsigned long long *head, int64_t *tile_cost, int32_t *claims,
+                             int64_t ntiles)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    if (i == 0 && head)
+        *head = 0ull;
+    for (int64_t t = i; t < ntiles; t += stride) {
+        if (tile_cost)
+            tile_cost[t] = 0;
+        if (claims)
+            claims[t] = 0;
+    }
+}
+
+template <int POLICY, bool BATCH, bool DEFER>
+__global__ void __launch_bounds__(1024) render_kernel(RenderArgs a)
+{
+    __shared__ int32_t lds_next_row;
+    if constexpr (POLICY == POLICY_STATIC_ROWS || POLICY == POLICY_ALTERNATING_ROWS) {
+        if (threadIdx.x == 0)
+            lds_next_row = 0;
+        __syncthreads();
+    }
+    const uint32_t lane = lane_id();
+
+    // ---- wave-uniform state of the current work item ----------------------
+    int32_t s_view = 0;          // view of the item
+    int32_t s_x0 = 0, s_y0 = 0;  // item origin (column, row)
+    int32_t s_w = 1;             // item width in pixels
+    int32_t s_next = 0, s_cnt = 0; // next pixel index, pixels in the item
+    int64_t s_tile = 0;          // tile id (for the cost log)
+    int64_t q_next = 0;          // FCFS: next queue slot of the current claim
+    int32_t q_left = 0;          // FCFS: slots left in the current claim
+    int32_t taken = 0;           // items taken (statistics)
+    bool exhausted = false;
+    bool grid_done = false;
+
+    // Next work item of this wave, or false when the source is empty.
+    auto next_item = [&]() -> bool {
+        if constexpr (POLICY == POLICY_FCFS_TILES || POLICY == POLICY_ORDERED_TILES ||
+                      POLICY == POLICY_GRID_TILES) {
+            for (;;) {
+                int64_t t;
+                if constexpr (POLICY == POLICY_GRID_TILES) {
+                    if (grid_done)
+                        return false;
+                    grid_done = true;
+                    t = (int64_t)blockIdx.x + (int64_t)blockIdx.y * gridDim.x;
+                    if (t >= a.ntiles)
+                        return false;
+                } else {
+                    if (q_left == 0) {
+                        unsigned long long q = 0;
+                        if (lane == 0)
+                            q = atomicAdd(a.head, (unsigned long long)a.grain);
+                        int64_t qb = bcast_i64((int64_t)q);
+                        if (qb >= a.ntiles)
+                            return false;
+                        q_next = qb;
+                        int64_t left = a.ntiles - qb;
+                        q_left = (int32_t)(left < a.grain ? left : a.grain);
+                    }
+                    int64_t slot = q_next++;
+                    --q_left;
+                    if constexpr (POLICY == POLICY_ORDERED_TILES) {
+                        t = (int64_t)a.order[slot];
+                        if (t < 0 || t >= a.ntiles)
+                            continue; // not a tile id: skipped, never dereferenced
+                    } else {
+                        t = slot;
+                    }
+                }
+                if (a.claims && lane == 0)
+                    atomicAdd(&a.claims[t], 1);
+                int32_t v = 0;
+                int64_t tile_off;
+                int32_t tiles_x, vm, vn;
+                if constexpr (BATCH) {
+                    v = bcast_i32(find_view(a.views, a.nviews, t));
+                    tile_off = a.views[v].tile_off;
+                    tiles_x = a.views[v].tiles_x;
+                    vm = a.views[v].m;
+                    vn = a.views[v].n;
+                } else {
+                    tile_off = a.v0.tile_off;
+                    tiles_x = a.v0.tiles_x;
+                    vm = a.v0.m;
+                    vn = a.v0.n;
+                }
+                int64_t lt = t - tile_off;
+                int32_t ty = (int32_t)(lt / tiles_x);
+                int32_t tx = (int32_t)(lt - (int64_t)ty * tiles_x);
+                int32_t x0 = tx * a.tile_w, y0 = ty * a.tile_h;
+                int32_t w = vn - x0 < a.tile_w ? vn - x0 : a.tile_w;
+                int32_t h = vm - y0 < a.tile_h ? vm - y0 : a.tile_h;
+                s_view = v;
+                s_x0 = x0;
+                s_y0 = y0;
+                s_w = w;
+                s_next = 0;
+                s_cnt = w * h;
+                s_tile = t;
+                ++taken;
+                return true;
+            }
+        } else {
+            // Row policies: a workgroup is one worker r of W = gridDim.x.
+            const int32_t m = a.v0.m;
+            const int32_t W = (int32_t)gridDim.x;
+            const int32_t r = (int32_t)blockIdx.x;
+            const int32_t q = m / W;
+            int32_t k = 0;
+            if (lane == 0)
+                k = atomicAdd(&lds_next_row, 1);
+            k = bcast_i32(k);
+            int32_t row;
+            if constexpr (POLICY == POLICY_STATIC_ROWS) {
+                // Sec. III-A: S_r = q*r, E_r = q*(r+1) - 1, last worker + (m mod W).
+                int32_t cnt = q + (r == W - 1 ? m % W : 0);
+                if (k >= cnt)
+                    return false;
+                row = q * r + k;
+            } else {
+                // Sec. III-C: rows r + k*W for k < q; worker 0 also does rows q*W .. m-1.
+                int32_t cnt = q + (r == 0 ? m - q * W : 0);
+                if (k >= cnt)
+                    return false;
+                row = k < q ? r + k * W : q * W + (k - q);
+            }
+            s_view = 0;
+            s_x0 = 0;
+            s_y0 = row;
+            s_w = a.v0.n;
+            s_next = 0;
+            s_cnt = a.v0.n;
+            s_tile = row;
+            ++taken;
+            return true;
+        }
+    };
+
+    // ---- per-lane state ------------------------------------------------------
+    double x = 0.0, y = 0.0, cx = 0.0, cy = 0.0;
+    double xs = 0.0, ys = 0.0; // snapshot at the start of a deferred block
+    double R2 = a.v0.R2;
+    uint32_t start = 0, deadline = 0; // wave-iteration of z_0 and of z_{max_iter-1}
+    int64_t oidx = 0;                 // flat output index
+    int64_t ltile = 0;                // tile of the pixel (cost log)
+    bool active = false, pending = false, safe = false;
+    uint64_t acc = 0;                 // sum of counts finished by this lane
+    uint32_t W = 0;                   // wave iteration counter (uniform)
+
+    auto refill = [&]() {
+        for (;;) {
+            uint64_t need = ballot(!active);
+            if (need == 0 || exhausted)
+                break;
+            if (s_next >= s_cnt) {
+                if (!next_item())
+                    exhausted = true;
+                continue;
+            }
+            const int32_t avail = s_cnt - s_next;
+            const int32_t k = (int32_t)__popcll(need);
+            const int32_t take = k < avail ? k : avail;
+            const uint32_t rk = rank_in(need);
+            if (!active && (int32_t)rk < take) {
+                ViewDesc vv;
+                if constexpr (BATCH)
+                    vv = a.views[s_view];
+                else
+                    vv = a.v0;
+                const ViewDesc *vd = &vv;
+                const int32_t p = s_next + (int32_t)rk;
+                const int32_t i = s_y0 + p / s_w;
+                const int32_t j = s_x0 + p % s_w;
+                const double offx = ((double)j + 0.5) - 0.5 * (double)vd->n;
+                const double offy = ((double)i + 0.5) - 0.5 * (double)vd->m;
+                const double px = offx * vd->dx;
+                const double py = offy * vd->dy;
+                cx = vd->cx0 + px;
+                cy = vd->cy0 + py;
+                x = 0.0;
+                y = 0.0;
+                if constexpr (BATCH)
+                    R2 = vd->R2;
+                start = W;
+                deadline = W + (uint32_t)(vd->max_iter - 1);
+                oidx = vd->out_off + (int64_t)i * vd->n + j;
+                ltile = s_tile;
+                if constexpr (DEFER) {
+                    const double cc = cx * cx + cy * cy;
+                    safe = cc <= vd->safe2;
+                }
+                pending = false;
+                active = true;
+            }
+            s_next += take;
+        }
+    };
+
+    auto finalize = [&](bool fin, bool esc) {
+        if (fin) {
+            const uint32_t cnt = esc ? (W - start) : (deadline - start + 1u);
+            a.out[oidx] = (int32_t)cnt;
+            if (a.tile_cost)
+                atomicAdd((unsigned long long *)&a.tile_cost[ltile], (unsigned long long)cnt);
+            acc += cnt;
+            active = false;
+            pending = false;
+        }
+    };
+
+    const uint32_t K = (uint32_t)a.block_iters;
+    const uint32_t P = (uint32_t)a.young_iters;
+
+    for (;;) {
+        refill();
+        if (ballot(active) == 0)
+            break;
+        // iterations until the first lane reaches z_{max_iter-1}
+        const uint32_t budget = wave_min_u32(active ? deadline - W : 0xffffffffu);
+
+        if constexpr (DEFER) {
+            const bool needc = active && (pending || !safe || (W - start) < P);
+            if (ballot(needc) == 0 && budget > 0) {
+                // Deferred block: L updates with no test.  Every active lane is
+                // "safe": once |z|^2 > R^2 its modulus keeps growing (or the
+                // values become inf/NaN), so a single test at the end of the
+                // block tells whether the escape happened inside the block.
+                const uint32_t L = budget < K ? budget : K;
+                xs = x;
+                ys = y;
+                const uint32_t L4 = L >> 2;
+                for (uint32_t u = 0; u < L4; ++u) {
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const double xx = x * x;
+                        const double yy = y * y;
+                        const double t = x * y;
+                        x = (xx - yy) + cx;
+                        y = __builtin_fma(2.0, t, cy);
+                    }
+                }
+                for (uint32_t u = 0; u < (L & 3u); ++u) {
+                    const double xx = x * x;
+                    const double yy = y * y;
+                    const double t = x * y;
+                    x = (xx - yy) + cx;
+                    y = __builtin_fma(2.0, t, cy);
+                }
+                W += L;
+                const double s = x * x + y * y;
+                const bool e = active && !(s <= R2);
+                if (e) {
+                    // escaped somewhere in the block: rewind and replay with tests
+                    x = xs;
+                    y = ys;
+                    start += L;
+                    deadline += L;
+                    pending = true;
+                }
+                const bool dl = active && !e && deadline == W;
+                finalize(dl, false);
+                continue;
+            }
+        }
+
+        // Checked mode: test after every update, stop at the first escape or
+        // when some lane reaches its last state z_{max_iter-1}.
+        const uint32_t limit = DEFER ? (budget < K ? budget : K) : budget;
+        uint32_t steps = 0;
+        const uint64_t amask = ballot(active);
+        uint64_t emask;
+        for (;;) {
+            const double xx = x * x;
+            const double yy = y * y;
+            const double s = xx + yy;
+            emask = ballot(s > R2) & amask;
+            if (emask != 0 || steps == limit)
+                break;
+            const double t = x * y;
+            x = (xx - yy) + cx;
+            y = __builtin_fma(2.0, t, cy);
+            ++W;
+            ++steps;
+        }
+        const bool e = (emask >> lane) & 1u;
+        finalize(e || (active && deadline == W), e);
+    }
+
+    if (a.stats) {
+        const uint64_t tot = wave_sum_u64(acc);
+        if (lane == 0) {
+            atomicAdd((unsigned long long *)&a.stats[0], (unsigned long long)W);
+            atomicAdd((unsigned long long *)&a.stats[1], (unsigned long long)tot);
+            atomicAdd((unsigned long long *)&a.stats[2], 1ull);
+            atomicAdd((unsigned long long *)&a.stats[3], (unsigned long long)taken);
+        }
+    }
+}
+
+// ---- launch helpers (host) ---------------------------------------------------
+
+template <int POLICY, bool BATCH, bool DEFER>
+static hipError_t launch_one(const RenderArgs &a, dim3 grid, dim3 block, hipStream_t s)
+{
+    hipLaunchKernelGGL((render_kernel<POLICY, BATCH, DEFER>), grid, block, 0, s, a);
+    return hipGetLastError();
+}
+
+template <int POLICY, bool BATCH>
+static hipError_t launch_defer(const RenderArgs &a, bool defer, dim3 grid, dim3 block,
+                               hipStream_t s)
+{
+    return defer ? launch_one<POLICY, BATCH, true>(a, grid, block, s)
+                 : launch_one<POLICY, BATCH, false>(a, grid, block, s);
+}
+
+hipError_t launch_render(const RenderArgs &a, int policy, bool batch, bool defer, dim3 grid,
+                         dim3 block, hipStream_t s)
+{
+    if (batch) {
+        switch (policy) {
+        case POLICY_FCFS_TILES:
+            return launch_defer<POLICY_FCFS_TILES, true>(a, defer, grid, block, s);
+        case POLICY_ORDERED_TILES:
+            return launch_defer<POLICY_ORDERED_TILES, true>(a, defer, grid, block, s);
+        case POLICY_GRID_TILES:
+            return launch_defer<POLICY_GRID_TILES, true>(a, defer, grid, block, s);
+        default:
+            return hipErrorInvalidValue;
+        }
+    }
+    switch (policy) {
+    case POLICY_FCFS_TILES:
+        return launch_defer<POLICY_FCFS_TILES, false>(a, defer, grid, block, s);
+    case POLICY_STATIC_ROWS:
+        return launch_defer<POLICY_STATIC_ROWS, false>(a, defer, grid, block, s);
+    case POLICY_ALTERNATING_ROWS:
+        return launch_defer<POLICY_ALTERNATING_ROWS, false>(a, defer, grid, block, s);
+    case POLICY_ORDERED_TILES:
+        return launch_defer<POLICY_ORDERED_TILES, false>(a, defer, grid, block, s);
+    case POLICY_GRID_TILES:
+        return launch_defer<POLICY_GRID_TILES, false>(a, defer, grid, block, s);
+    default:
+        return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_clear(unsigned long long *head, int64_t *tile_cost, int32_t *claims,
+                        int64_t ntiles, hipStream_t s)
+{
+    int64_t blocks = (ntiles + 255) / 256;
+    if (blocks < 1)
+        blocks = 1;
+    if (blocks > 4096)
+        blocks = 4096;
+    hipLaunchKernelGGL(clear_kernel, dim3((unsigned)blocks), dim3(256), 0, s, head, tile_cost,
+                       claims, ntiles);
+    return hipGetLastError();
+}
+
+int persistent_blocks_per_cu(int policy, bool batch, bool defer, int threads)
+{
+    int nb = 0;
+    hipError_t e = hipErrorInvalidValue;
+#define MANDEL_OCC(P, B, D)                                                                    \
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, render_kernel<P, B, D>, threads, 0)
+    if (batch) {
+        if (policy == POLICY_ORDERED_TILES) {
+            if (defer) MANDEL_OCC(POLICY_ORDERED_TILES, true, true);
+            else MANDEL_OCC(POLICY_ORDERED_TILES, true, false);
+        } else {
+            if (defer) MANDEL_OCC(POLICY_FCFS_TILES, true, true);
+            else MANDEL_OCC(POLICY_FCFS_TILES, true, false);
+        }
+    } else {
+        if (policy == POLICY_ORDERED_TILES) {
+            if (defer) MANDEL_OCC(POLICY_ORDERED_TILES, false, true);
+            else MANDEL_OCC(POLICY_ORDERED_TILES, false, false);
+        } else {
+            if (defer) MANDEL_OCC(POLICY_FCFS_TILES, false, true);
+            else MANDEL_OCC(POLICY_FCFS_TILES, false, false);
+        }
+    }
+#undef MANDEL_OCC
+    if (e != hipSuccess || nb < 1)
+        return 1;
+    return nb;
+}
+
+} // namespace mandel

@@ -1,0 +1,72 @@
+"""Host-side checks of libmandel.so that need no GPU: it loads, exports every
+entry point that include/mandel.h declares, and rejects bad arguments before
+touching the device."""
+import ctypes
+import subprocess
+
+import pytest
+
+from paper_2007_00745_amd import native
+
+
+def test_library_exports_header_symbols():
+    L = native.lib()
+    names = native.exported_names()
+    assert "mandel_render" in names and "mandel_render_sched" in names
+    for nm in names:
+        assert hasattr(L, nm), f"{nm} declared in mandel.h but not exported"
+    out = subprocess.run(["nm", "-D", "--defined-only", native.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = {ln.split()[-1] for ln in out.splitlines() if " T " in ln}
+    missing = [nm for nm in names if nm not in exported]
+    assert not missing, missing
+
+
+def test_version_and_tile_count():
+    L = native.lib()
+    assert L.mandel_version().startswith(b"mandel-gfx950")
+    assert native.tile_count(480, 640) == 60 * 10
+    assert native.tile_count(8192, 8192) == 1024 * 128
+    assert native.tile_count(9, 65, 64, 8) == 2 * 2
+    assert native.tile_count(0, 65) == 0
+
+
+def _call(win=(-0.5, 0.0, 0.01, 0.01), m=8, n=8, mi=10, R=2.0, out=0x1000, sched=None):
+    L = native.lib()
+    w = native.Window(*win)
+    if sched is None:
+        return L.mandel_render(ctypes.byref(w), m, n, mi, R, out, None)
+    return L.mandel_render_sched(ctypes.byref(w), m, n, mi, R, out, ctypes.byref(sched), None)
+
+
+@pytest.mark.parametrize("kw", [
+    dict(m=-1), dict(n=-5), dict(mi=0), dict(mi=(1 << 30) + 1), dict(R=0.0), dict(R=-2.0),
+    dict(R=float("nan")), dict(R=float("inf")), dict(R=1e151),
+    dict(win=(float("nan"), 0.0, 0.01, 0.01)), dict(win=(0.0, 0.0, 0.0, 0.01)),
+    dict(win=(0.0, 0.0, 0.01, -0.01)), dict(win=(0.0, float("inf"), 0.01, 0.01)),
+    dict(win=(1e308, 0.0, 1e307, 0.01), n=100), dict(m=1 << 20, n=1 << 20),
+])
+def test_invalid_arguments(kw):
+    assert _call(**kw) == native.EINVAL
+    assert native.lib().mandel_last_error()
+
+
+def test_null_pointers():
+    L = native.lib()
+    assert L.mandel_render(None, 8, 8, 10, 2.0, 0x1000, None) == native.EINVAL
+    assert _call(out=None) == native.EINVAL
+
+
+def test_empty_image_is_a_no_op():
+    assert _call(m=0, out=None) == native.OK
+    assert _call(n=0, out=None) == native.OK
+
+
+@pytest.mark.parametrize("s", [
+    dict(policy=7), dict(policy=1), dict(policy=3), dict(tile_w=-1), dict(grain=-3),
+    dict(waves_per_group=17), dict(check_every=2), dict(block_iters=2000), dict(young_iters=-1),
+    dict(workers=-1),
+])
+def test_invalid_schedules(s):
+    sched = native.make_sched(**s)
+    assert _call(sched=sched) == native.EINVAL

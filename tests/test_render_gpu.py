@@ -1,0 +1,210 @@
+"""GPU parity: counts from libmandel.so (through the C ABI) against the CPU
+oracle, element by element and bit for bit (paper Sec. I, Eq. (1)-(2)), for
+every policy of the kernel family (Sec. III-A/B/C and the tile orders), both
+escape-test modes, ragged tile edges, degenerate sizes and radii, and the
+full-size 8192 x 8192 view on sampled pixels."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import partition
+from paper_2007_00745_amd import native, workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def _log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def gpu_render(view, **sched):
+    _log(f"render {view.m}x{view.n} it={view.max_iter} R={view.R} {sched}")
+    if sched:
+        out = native.render_sched(view.window, view.m, view.n, view.max_iter, view.R, **sched)
+    else:
+        out = native.render(view.window, view.m, view.n, view.max_iter, view.R)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+def ref(view, threads=8):
+    if view.pixels * min(view.max_iter, 2000) < 4e8:
+        return oracle.render(view.window, view.m, view.n, view.max_iter, view.R)
+    return oracle.render_parallel(view.window, view.m, view.n, view.max_iter, view.R, threads)[0]
+
+
+@pytest.fixture(scope="module")
+def c1_ref():
+    return ref(workloads.c1())
+
+
+def test_c1_default(c1_ref):
+    got = gpu_render(workloads.c1())
+    assert np.array_equal(got, c1_ref)
+
+
+SCHEDS = [
+    dict(policy="fcfs"),
+    dict(policy="fcfs", check_every=1),
+    dict(policy="fcfs", tile_w=32, tile_h=4, grain=3),
+    dict(policy="fcfs", tile_w=64, tile_h=1, waves_per_group=1),
+    dict(policy="fcfs", tile_w=128, tile_h=16, block_iters=7, young_iters=0),
+    dict(policy="fcfs", block_iters=1, young_iters=1),
+    dict(policy="fcfs", block_iters=1024, young_iters=0, waves_per_group=16),
+    dict(policy="grid"),
+    dict(policy="grid", check_every=1, tile_w=16, tile_h=16),
+    dict(policy="static", workers=7),
+    dict(policy="static", workers=480, check_every=1),
+    dict(policy="static", workers=1000, waves_per_group=2),
+    dict(policy="alternating", workers=13),
+    dict(policy="alternating", workers=256, waves_per_group=8),
+    dict(policy="alternating", workers=1, waves_per_group=16),
+]
+
+
+@pytest.mark.parametrize("sched", SCHEDS, ids=[str(s) for s in SCHEDS])
+def test_c1_every_schedule(c1_ref, sched):
+    assert np.array_equal(gpu_render(workloads.c1(), **sched), c1_ref)
+
+
+def test_c1_ordered_permutations(c1_ref):
+    v = workloads.c1()
+    nt = native.tile_count(v.m, v.n)
+    rng = np.random.default_rng(11)
+    for perm in (np.arange(nt)[::-1].copy(), rng.permutation(nt)):
+        order = torch.tensor(perm, dtype=torch.int32, device="cuda")
+        claims = torch.zeros(nt, dtype=torch.int32, device="cuda")
+        got = gpu_render(v, policy="ordered", order=order, claims=claims)
+        assert np.array_equal(got, c1_ref)
+        assert torch.all(claims == 1)
+
+
+def test_claims_and_costs(c1_ref):
+    # every tile claimed exactly once; per-tile cost log equals the sum of its counts
+    v = workloads.c1()
+    for tw, th, g in ((64, 8, 1), (48, 5, 4), (640, 1, 2)):
+        nt = native.tile_count(v.m, v.n, tw, th)
+        claims = torch.full((nt,), 7, dtype=torch.int32, device="cuda")
+        cost = torch.full((nt,), -1, dtype=torch.int64, device="cuda")
+        stats = torch.zeros(4, dtype=torch.int64, device="cuda")
+        got = gpu_render(v, tile_w=tw, tile_h=th, grain=g, claims=claims, tile_cost=cost,
+                         stats=stats)
+        assert np.array_equal(got, c1_ref)
+        assert torch.all(claims == 1)
+        ty, tx = -(-v.m // th), -(-v.n // tw)
+        pad = np.zeros((ty * th, tx * tw), dtype=np.int64)
+        pad[:v.m, :v.n] = c1_ref
+        want = pad.reshape(ty, th, tx, tw).sum(axis=(1, 3)).ravel()
+        assert np.array_equal(cost.cpu().numpy(), want)
+        st = stats.cpu().numpy()
+        assert st[1] == c1_ref.sum()
+        assert st[3] == nt
+        assert st[0] * 64 >= st[1]  # lane iterations cannot exceed lane slots
+
+
+@pytest.mark.parametrize("m,n", [(1, 1), (1, 97), (97, 1), (9, 65), (37, 53), (129, 255)])
+@pytest.mark.parametrize("policy", ["fcfs", "grid", "static", "alternating"])
+def test_ragged_sizes(m, n, policy):
+    win = workloads.window_from_bounds(-2.1, 0.7, -1.3, 1.2, m, n)
+    v = workloads.View(win, m, n, 700, 2.0)
+    kw = dict(policy=policy)
+    if policy in ("static", "alternating"):
+        kw["workers"] = 5
+    assert np.array_equal(gpu_render(v, **kw), ref(v))
+
+
+def test_empty_views():
+    w = native.Window(-0.5, 0.0, 0.01, 0.01)
+    import ctypes
+    for m, n in ((0, 10), (10, 0), (0, 0)):
+        assert native.lib().mandel_render(ctypes.byref(w), m, n, 10, 2.0, None, None) == 0
+    torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("mi", [1, 2, 3, 17])
+def test_tiny_max_iter(mi):
+    v = workloads.View(workloads.c1().window, 48, 64, mi, 2.0)
+    v = workloads.View(workloads.window_from_bounds(-2, 1, -1.2, 1.2, 48, 64), 48, 64, mi, 2.0)
+    for ce in (0, 1):
+        got = gpu_render(v, check_every=ce)
+        assert np.array_equal(got, ref(v))
+        if mi == 1:
+            assert np.all(got == 1)
+
+
+@pytest.mark.parametrize("R", [0.5, 1.0, 1.999, 2.0, 2.5, 400.0, 1e150])
+def test_escape_radii(R):
+    # R < 2 never uses deferred tests; R >= 2 does where |c| is inside the safe disk
+    win = workloads.window_from_bounds(-2.6, 1.2, -1.6, 1.6, 96, 128)
+    v = workloads.View(win, 96, 128, 900, R)
+    want = ref(v)
+    for ce in (0, 1):
+        assert np.array_equal(gpu_render(v, check_every=ce), want)
+
+
+def test_exact_orbit_points():
+    # pixels placed exactly on the hand-derived orbits of the golden file
+    import os
+    rows = []
+    with open(os.path.join(os.path.dirname(__file__), "golden", "exact_orbits.txt")) as f:
+        for line in f:
+            line = line.split("#", 1)[0].strip()
+            if line:
+                rows.append([float(t) for t in line.split()])
+    for re_, im_, mi, R, exp in rows:
+        v = workloads.View((re_, im_, 1.0, 1.0), 1, 1, int(mi), R)  # 1x1: c = centre exactly
+        for ce in (0, 1):
+            assert gpu_render(v, check_every=ce)[0, 0] == int(exp), (re_, im_, mi, R)
+
+
+def test_zoomed_views_small():
+    views = workloads.c3_scaled(745, 64, scale=32)
+    for v in views[:24]:
+        want = ref(v)
+        assert np.array_equal(gpu_render(v), want)
+        assert np.array_equal(gpu_render(v, check_every=1, tile_w=32, tile_h=2), want)
+
+
+def test_row_partitions_cover_rows():
+    # the kernel's row ownership equals the paper's partitions: worker r of W renders
+    # exactly partition.naive_rows / alternating_rows (checked through the output:
+    # each row is written once and matches the oracle)
+    v = workloads.View(workloads.window_from_bounds(-2, 1, -1.2, 1.2, 101, 40), 101, 40, 300)
+    want = ref(v)
+    for W in (1, 2, 7, 100, 101, 150):
+        for pol, fn in (("static", partition.naive_rows), ("alternating", partition.alternating_rows)):
+            rows = sorted(r for k in range(W) for r in fn(v.m, W, k))
+            assert rows == list(range(v.m))
+            assert np.array_equal(gpu_render(v, policy=pol, workers=W), want)
+
+
+def test_nondefault_stream(c1_ref):
+    s = torch.cuda.Stream()
+    v = workloads.c1()
+    with torch.cuda.stream(s):
+        out = native.render(v.window, v.m, v.n, v.max_iter, v.R, stream=s)
+    s.synchronize()
+    assert np.array_equal(out.cpu().numpy(), c1_ref)
+
+
+def test_c2_full_size_sampled():
+    # The 8192 x 8192, max_iter 10000 view in the default launch: sampled pixels
+    # (three whole rows, tile corners and 6000 random pixels) against the oracle,
+    # plus invariants on the whole image.
+    v = workloads.c2()
+    got = gpu_render(v)
+    assert got.min() >= 1 and got.max() == v.max_iter
+    assert np.array_equal(got, got[::-1, :])  # conjugation symmetry
+    rng = np.random.default_rng(2007)
+    rows = [0, v.m // 2 - 1, v.m // 3]
+    idx = [np.arange(r * v.n, (r + 1) * v.n) for r in rows]
+    ty, tx = np.meshgrid(np.arange(0, v.m, 8), np.arange(0, v.n, 64), indexing="ij")
+    corners = (ty * v.n + tx).ravel()
+    idx.append(rng.choice(corners, 2000, replace=False))
+    idx.append(rng.integers(0, v.m * v.n, 6000))
+    idx = np.concatenate(idx)
+    want = oracle.render_pixels(v.window, v.m, v.n, v.max_iter, v.R, idx, threads=16)
+    assert np.array_equal(got.ravel()[idx], want)
