@@ -95,8 +95,8 @@ typedef struct mandel_sched {
     int32_t waves_per_group; /* wavefronts per workgroup, 1..16 [4] */
     int32_t check_every;     /* 1 = test |z|^2 > R^2 after every update only;
                                 0 = also allow deferred blocks of tests [0] */
-    int32_t block_iters;     /* deferred-test block length K, 1..1024 [32] */
-    int32_t young_iters;     /* pixels younger than this are tested every update [16] */
+    int32_t block_iters;     /* longest deferred-test block K, 1..1024 [256] */
+    int32_t young_iters;     /* pixels younger than this are tested every update [8] */
     int32_t reserved;
     const int32_t *order;    /* device int32[ntiles], ORDERED_TILES only: a permutation */
     int64_t *tile_cost;      /* device int64[ntiles] or NULL: sum of counts per tile

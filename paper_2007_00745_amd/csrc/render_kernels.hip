@@ -59,13 +59,24 @@ __device__ __forceinline__ int64_t bcast_i64(int64_t v)
     return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
+// Minimum over the 64 lanes (exec must be full): DPP row shifts reduce each
+// 16-lane row, two row broadcasts fold the rows, lane 63 holds the result.
+#define MANDEL_DPP_MIN(v, ctrl, rmask)                                                        \
+    do {                                                                                    \
+        const uint32_t o_ = (uint32_t)__builtin_amdgcn_update_dpp((int)(v), (int)(v), ctrl,  \
+                                                                  rmask, 0xf, false);       \
+        (v) = (v) < o_ ? (v) : o_;                                                          \
+    } while (0)
+
 __device__ __forceinline__ uint32_t wave_min_u32(uint32_t v)
 {
-    for (int off = 32; off >= 1; off >>= 1) {
-        uint32_t o = (uint32_t)__shfl_xor((int)v, off, 64);
-        v = v < o ? v : o;
-    }
-    return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
+    MANDEL_DPP_MIN(v, 0x111, 0xf); // row_shr:1
+    MANDEL_DPP_MIN(v, 0x112, 0xf); // row_shr:2
+    MANDEL_DPP_MIN(v, 0x114, 0xf); // row_shr:4
+    MANDEL_DPP_MIN(v, 0x118, 0xf); // row_shr:8
+    MANDEL_DPP_MIN(v, 0x142, 0xa); // row_bcast:15 into rows 1 and 3
+    MANDEL_DPP_MIN(v, 0x143, 0xc); // row_bcast:31 into rows 2 and 3
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
 }
 
 __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v)
@@ -125,6 +136,7 @@ __global__ void __launch_bounds__(1024) render_kernel(RenderArgs a)
     int32_t s_x0 = 0, s_y0 = 0;  // item origin (column, row)
     int32_t s_w = 1;             // item width in pixels
     int32_t s_next = 0, s_cnt = 0; // next pixel index, pixels in the item
+    int32_t s_in = 0, s_jn = 0;  // next pixel as (row, column) within the item (s_w >= 64)
     int64_t s_tile = 0;          // tile id (for the cost log)
     int64_t q_next = 0;          // FCFS: next queue slot of the current claim
     int32_t q_left = 0;          // FCFS: slots left in the current claim
@@ -195,6 +207,8 @@ __global__ void __launch_bounds__(1024) render_kernel(RenderArgs a)
                 s_y0 = y0;
                 s_w = w;
                 s_next = 0;
+                s_in = 0;
+                s_jn = 0;
                 s_cnt = w * h;
                 s_tile = t;
                 ++taken;
@@ -229,6 +243,8 @@ __global__ void __launch_bounds__(1024) render_kernel(RenderArgs a)
             s_y0 = row;
             s_w = a.v0.n;
             s_next = 0;
+            s_in = 0;
+            s_jn = 0;
             s_cnt = a.v0.n;
             s_tile = row;
             ++taken;
@@ -268,9 +284,23 @@ __global__ void __launch_bounds__(1024) render_kernel(RenderArgs a)
                 else
                     vv = a.v0;
                 const ViewDesc *vd = &vv;
-                const int32_t p = s_next + (int32_t)rk;
-                const int32_t i = s_y0 + p / s_w;
-                const int32_t j = s_x0 + p % s_w;
+                // pixel s_next + rk of the item, row-major within it
+                int32_t i, j;
+                if (s_w >= 64) {
+                    // rk < 64 <= s_w: at most one wrap past the item's right edge
+                    j = s_jn + (int32_t)rk;
+                    i = s_in;
+                    if (j >= s_w) {
+                        j -= s_w;
+                        i += 1;
+                    }
+                } else {
+                    const int32_t p = s_next + (int32_t)rk;
+                    i = p / s_w;
+                    j = p - i * s_w;
+                }
+                i += s_y0;
+                j += s_x0;
                 const double offx = ((double)j + 0.5) - 0.5 * (double)vd->n;
                 const double offy = ((double)i + 0.5) - 0.5 * (double)vd->m;
                 const double px = offx * vd->dx;
@@ -293,6 +323,13 @@ __global__ void __launch_bounds__(1024) render_kernel(RenderArgs a)
                 active = true;
             }
             s_next += take;
+            if (s_w >= 64) {
+                s_jn += take;
+                if (s_jn >= s_w) {
+                    s_jn -= s_w;
+                    s_in += 1;
+                }
+            }
         }
     };
 
@@ -308,82 +345,130 @@ __global__ void __launch_bounds__(1024) render_kernel(RenderArgs a)
         }
     };
 
-    const uint32_t K = (uint32_t)a.block_iters;
+    const uint32_t K = (uint32_t)a.block_iters; // longest deferred block
     const uint32_t P = (uint32_t)a.young_iters;
+    const uint32_t Kmin = K < 8u ? K : 8u;
+    uint32_t Kc = K; // current deferred block length (halved after a replay, doubled after a clean block)
 
+    // One update z <- z^2 + c, in the contract's operation order.
+    auto update = [&]() {
+        const double xx = x * x;
+        const double yy = y * y;
+        const double t = x * y;
+        x = (xx - yy) + cx;
+        y = __builtin_fma(2.0, t, cy);
+    };
+    // One tested update: mask of lanes whose current state has |z|^2 > R^2
+    // (tested before the update, so the count of such a lane is its age now).
+    auto tested_update = [&]() -> uint64_t {
+        const double xx = x * x;
+        const double yy = y * y;
+        const uint64_t m = ballot(xx + yy > R2);
+        const double t = x * y;
+        x = (xx - yy) + cx;
+        y = __builtin_fma(2.0, t, cy);
+        return m;
+    };
+
+    // Invariant at the top of each round: every active lane holds the state
+    // z_n, n = W - start, not yet tested, and W <= deadline.
     for (;;) {
         refill();
-        if (ballot(active) == 0)
+        const uint64_t amask = ballot(active);
+        if (amask == 0)
             break;
-        // iterations until the first lane reaches z_{max_iter-1}
-        const uint32_t budget = wave_min_u32(active ? deadline - W : 0xffffffffu);
+        // updates until the first lane reaches its last state z_{max_iter-1}
+        uint32_t budget = wave_min_u32(active ? deadline - W : 0xffffffffu);
 
         if constexpr (DEFER) {
             const bool needc = active && (pending || !safe || (W - start) < P);
+            // (budget == 0 means some lane sits at an untested last state: the
+            // checked mode below tests it)
             if (ballot(needc) == 0 && budget > 0) {
-                // Deferred block: L updates with no test.  Every active lane is
-                // "safe": once |z|^2 > R^2 its modulus keeps growing (or the
-                // values become inf/NaN), so a single test at the end of the
-                // block tells whether the escape happened inside the block.
-                const uint32_t L = budget < K ? budget : K;
-                xs = x;
-                ys = y;
-                const uint32_t L4 = L >> 2;
-                for (uint32_t u = 0; u < L4; ++u) {
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) {
-                        const double xx = x * x;
-                        const double yy = y * y;
-                        const double t = x * y;
-                        x = (xx - yy) + cx;
-                        y = __builtin_fma(2.0, t, cy);
+                // Steady state: blocks of L untested updates.  Every active lane
+                // is "safe": once |z|^2 > R^2 its modulus keeps growing (or turns
+                // inf/NaN, which never becomes finite again), so one test at the
+                // end of a block tells whether the escape happened inside it.
+                while (budget > 0) {
+                    const uint32_t L = budget < Kc ? budget : Kc;
+                    xs = x;
+                    ys = y;
+                    for (uint32_t u = 0; u < (L >> 2); ++u) {
+                        update();
+                        update();
+                        update();
+                        update();
                     }
+                    for (uint32_t u = 0; u < (L & 3u); ++u)
+                        update();
+                    W += L;
+                    budget -= L;
+                    const double sq = x * x + y * y;
+                    const uint64_t em = ballot(!(sq <= R2)) & amask;
+                    if (em != 0) {
+                        if ((em >> lane) & 1u) {
+                            // rewind to the block start and replay it with tests
+                            x = xs;
+                            y = ys;
+                            start += L;
+                            deadline += L;
+                            pending = true;
+                        }
+                        // escapes are near: shorter blocks waste less on replays
+                        Kc = Kc >> 1 < Kmin ? Kmin : Kc >> 1;
+                        break;
+                    }
+                    Kc = Kc << 1 > K ? K : Kc << 1;
                 }
-                for (uint32_t u = 0; u < (L & 3u); ++u) {
-                    const double xx = x * x;
-                    const double yy = y * y;
-                    const double t = x * y;
-                    x = (xx - yy) + cx;
-                    y = __builtin_fma(2.0, t, cy);
-                }
-                W += L;
-                const double s = x * x + y * y;
-                const bool e = active && !(s <= R2);
-                if (e) {
-                    // escaped somewhere in the block: rewind and replay with tests
-                    x = xs;
-                    y = ys;
-                    start += L;
-                    deadline += L;
-                    pending = true;
-                }
-                const bool dl = active && !e && deadline == W;
-                finalize(dl, false);
+                // lanes now at z_{max_iter-1} with no escape so far: count = max_iter
+                finalize(active && !pending && deadline == W, false);
                 continue;
             }
         }
 
-        // Checked mode: test after every update, stop at the first escape or
-        // when some lane reaches its last state z_{max_iter-1}.
-        const uint32_t limit = DEFER ? (budget < K ? budget : K) : budget;
-        uint32_t steps = 0;
-        const uint64_t amask = ballot(active);
-        uint64_t emask;
-        for (;;) {
-            const double xx = x * x;
-            const double yy = y * y;
-            const double s = xx + yy;
-            emask = ballot(s > R2) & amask;
-            if (emask != 0 || steps == limit)
-                break;
-            const double t = x * y;
-            x = (xx - yy) + cx;
-            y = __builtin_fma(2.0, t, cy);
-            ++W;
-            ++steps;
+        // Checked mode: groups of four tested updates.  A lane's count is the
+        // age at its first set mask bit, provided that is not past its deadline.
+        // When only young lanes asked for it, P tested updates suffice; replays
+        // and unsafe lanes keep it until an event (or K updates) ends it.
+        uint32_t climit = K;
+        if constexpr (DEFER) {
+            if (ballot(active && (pending || !safe)) == 0)
+                climit = P;
         }
-        const bool e = (emask >> lane) & 1u;
-        finalize(e || (active && deadline == W), e);
+        uint32_t done = 0;
+        for (;;) {
+            const uint32_t W0 = W;
+            const uint64_t m0 = tested_update();
+            const uint64_t m1 = tested_update();
+            const uint64_t m2 = tested_update();
+            const uint64_t m3 = tested_update();
+            W += 4;
+            const uint64_t any = (m0 | m1 | m2 | m3) & amask;
+            if (any != 0 || budget < 4) {
+                const uint32_t ke = ((m0 >> lane) & 1u) ? 0u
+                                  : ((m1 >> lane) & 1u) ? 1u
+                                  : ((m2 >> lane) & 1u) ? 2u
+                                  : ((m3 >> lane) & 1u) ? 3u : 4u;
+                const uint32_t kd = deadline - W0; // steps to the last state
+                const bool esc = active && ke < 4u && ke <= kd;
+                const bool dl = active && !esc && kd < 4u;
+                if (esc || dl) {
+                    const uint32_t cnt = esc ? (W0 + ke - start) : (deadline - start + 1u);
+                    a.out[oidx] = (int32_t)cnt;
+                    if (a.tile_cost)
+                        atomicAdd((unsigned long long *)&a.tile_cost[ltile],
+                                  (unsigned long long)cnt);
+                    acc += cnt;
+                    active = false;
+                    pending = false;
+                }
+                break;
+            }
+            budget -= 4;
+            done += 4;
+            if (DEFER && done >= climit)
+                break; // re-evaluate the mode
+        }
     }
 
     if (a.stats) {
