@@ -120,6 +120,152 @@ int mandel_render_sched(const mandel_window *w, int32_t m, int32_t n, int32_t ma
 /* Number of tiles of an m x n view under a tile shape (0 for an empty view). */
 int64_t mandel_tile_count(int32_t m, int32_t n, int32_t tile_w, int32_t tile_h);
 
+/* ---------------------------------------------------------------------------
+ * Batches: many views of different size, zoom and max_iter rendered by ONE
+ * persistent launch over one flat tile space (view k's tiles follow view
+ * k-1's, each view row-major over its own tile grid).  The paper renders one
+ * image per run (Sec. IV); batching is this library's extension of the same
+ * per-pixel definition, so every view's image equals mandel_render's.
+ * ------------------------------------------------------------------------- */
+typedef struct mandel_view {
+    mandel_window w;    /* window of this view */
+    int32_t m, n;       /* rows, columns (0 allowed: the view has no tiles) */
+    int32_t max_iter;   /* 1 .. 2^30 */
+    int32_t reserved;
+    double R;           /* escape radius, 0 < R <= 1e150 */
+    int64_t out_offset; /* element offset of this view's row-major image in out_base */
+} mandel_view;
+
+/* Launch shape of a plan; zero fields take the defaults in brackets. */
+typedef struct mandel_tuning {
+    int32_t tile_w, tile_h;  /* [64, 8] */
+    int32_t grain;           /* tiles per queue claim [1] */
+    int32_t waves_per_group; /* [4] */
+    int32_t block_iters;     /* [256] */
+    int32_t young_iters;     /* [8] */
+    int32_t groups;          /* persistent workgroups [fill the device] */
+    int32_t reserved;
+} mandel_tuning;
+
+typedef struct mandel_plan mandel_plan;
+
+/*
+ * mandel_plan_create -- validates the views (each as mandel_render would),
+ * builds the device view table and allocates the plan's queue head.
+ *   views   host array [nviews], copied; 1 <= nviews <= 2^24
+ *   tuning  host, or NULL for the defaults (see mandel_plan_autotune)
+ *   plan    receives the new plan; owned by the caller, freed by
+ *           mandel_plan_destroy.  Synchronous (allocates and copies).
+ * Output ranges of different views must not overlap (not checked).
+ */
+int mandel_plan_create(const mandel_view *views, int32_t nviews, const mandel_tuning *tuning,
+                       mandel_plan **plan);
+
+/* Plan geometry: total tiles, total pixels, and the tuning in force (any may be NULL). */
+int mandel_plan_info(const mandel_plan *plan, int64_t *ntiles, int64_t *npixels,
+                     mandel_tuning *tuning);
+
+/* Launch modes of a plan. */
+enum mandel_plan_mode {
+    MANDEL_PLAN_FCFS = 0,        /* queue in submission order (the fallback) */
+    MANDEL_PLAN_ORDERED = 1,     /* queue over the caller's permutation `order` */
+    MANDEL_PLAN_PROBE_LPT = 2,   /* probe features -> key = mean probe cost ->
+                                    descending order -> ordered render */
+    MANDEL_PLAN_LEARNED_LPT = 3  /* probe features -> cost-model MLP -> descending
+                                    order -> ordered render */
+};
+
+typedef struct mandel_launch {
+    int32_t mode;            /* enum mandel_plan_mode */
+    int32_t use_graph;       /* 1: capture the launch sequence once into a hipGraph
+                                (keyed by every pointer below and out_base) and
+                                replay it; 0: enqueue the kernels directly */
+    const int32_t *order;    /* device int32[ntiles], ORDERED: a permutation of tile ids */
+    const float *mlp;        /* device float[MANDEL_MLP_PARAMS], LEARNED_LPT: the cost model */
+    int64_t *tile_cost;      /* device int64[ntiles] or NULL: sum of counts per tile */
+    uint64_t *stats;         /* device uint64[4] or NULL (as in mandel_sched) */
+} mandel_launch;
+
+/*
+ * mandel_plan_launch -- renders every view of the plan into out_base (device
+ * int32, each view at its out_offset) on `stream`.  All kernels of a launch
+ * go to that stream in order.  A plan has one queue: launches of the same
+ * plan must not overlap in time (same stream, or synchronise between them).
+ */
+int mandel_plan_launch(mandel_plan *plan, int32_t *out_base, const mandel_launch *args,
+                       void *stream);
+
+/* Frees the plan, its device buffers and its cached graphs (synchronises the device). */
+int mandel_plan_destroy(mandel_plan *plan);
+
+/* ---------------------------------------------------------------------------
+ * Learned tile ordering.  The paper balances load by handing out rows on
+ * demand (Sec. III-B) or interleaving them (Sec. III-C); here the queue order
+ * is chosen so that the most expensive tiles start first (longest-processing-
+ * time-first list scheduling), using a small FP32 cost model.  The order never
+ * changes a count, only when each tile runs.
+ * ------------------------------------------------------------------------- */
+#define MANDEL_FEATURES 68   /* per-tile features, see mandel_plan_features */
+#define MANDEL_HIDDEN 64     /* width of both hidden layers */
+/* Parameter vector of the cost model, FP32, in this order:
+ *   mu[68], inv_sd[68]     input standardisation x' = (x - mu) * inv_sd (not trained)
+ *   W1[64][68], b1[64]     h1 = relu(W1 x' + b1)
+ *   W2[64][64], b2[64]     h2 = relu(W2 h1 + b2)
+ *   w3[64], b3[1]          y  = w3 . h2 + b3   (predicted ln of the tile's sum of counts)
+ * 136 + 8641 floats; the 8641 after the standardisation are trained. */
+#define MANDEL_MLP_NORM 136
+#define MANDEL_MLP_PARAMS (136 + 64 * 68 + 64 + 64 * 64 + 64 + 64 + 1)
+
+/*
+ * mandel_plan_features -- per-tile features, device float[ntiles][68]:
+ *   [0], [1]  real and imaginary part of the tile's centre
+ *   [2]       log10 of the tile's width in the complex plane (columns * dx)
+ *   [3]       ln(max_iter)
+ *   [4 + 8r + k], r, k in 0..7: ln(1 + min(count, cap)) / ln(1 + cap) for the
+ *             probe pixel at column x0 + floor((k + 0.5) w / 8) and row
+ *             y0 + floor((r + 0.5) h / 8) of the (clipped) w x h tile, where
+ *             count is that pixel's escape-time count (same definition and
+ *             arithmetic as the render) and cap = min(max_iter, probe_cap).
+ *   probe_cap  1 .. 2^20, or 0 for 128.
+ */
+int mandel_plan_features(mandel_plan *plan, float *feat, int32_t probe_cap, void *stream);
+
+/* Cost-model inference: y[i] = model(x[i]) for i < n; x device float[n][68],
+ * y device float[n], params device float[MANDEL_MLP_PARAMS]. */
+int mandel_mlp_forward(const float *params, const float *x, int64_t n, float *y, void *stream);
+
+/* Device floats of scratch that mandel_mlp_train_step needs for a minibatch size. */
+int64_t mandel_mlp_work_floats(int32_t batch);
+
+/*
+ * mandel_mlp_train_step -- one Adam step (beta1 0.9, beta2 0.999, eps 1e-8,
+ * bias-corrected with step number t >= 1) on the mean squared error
+ *   L = (1/B) sum_b (model(x[idx[b]]) - target[idx[b]])^2
+ * over the minibatch idx (device int32[batch], entries in [0, n)).
+ *   params, adam_m, adam_v  device float[MANDEL_MLP_PARAMS] (standardisation
+ *                           entries are left unchanged), updated in place
+ *   x, target               device float[n][68], float[n]
+ *   loss                    device float[1] or NULL: L before the update
+ *   work                    device float[mandel_mlp_work_floats(batch)]
+ *   1 <= batch <= 4096, lr > 0.
+ */
+int mandel_mlp_train_step(float *params, float *adam_m, float *adam_v, int32_t t,
+                          const float *x, const float *target, const int32_t *idx,
+                          int32_t batch, float lr, float *loss, float *work, void *stream);
+
+/*
+ * mandel_order_desc -- perm (device int32[n]) becomes a permutation of 0..n-1
+ * whose keys (device float[n]) are non-increasing up to the bucket width:
+ * numbers are bucketed on a fixed grid of MANDEL_ORDER_BUCKETS - 1 equal
+ * buckets over [MANDEL_ORDER_KEY_LO, MANDEL_ORDER_KEY_HI] (keys outside go to
+ * the end buckets), NaN keys come after all numbers; the order inside one
+ * bucket is unspecified.  0 <= n < 2^31 (n == 0 does nothing).
+ */
+#define MANDEL_ORDER_BUCKETS 4096
+#define MANDEL_ORDER_KEY_LO (-2.0f)
+#define MANDEL_ORDER_KEY_HI 50.0f
+int mandel_order_desc(const float *keys, int64_t n, int32_t *perm, void *stream);
+
 /* Text of the last error on this thread ("" if none). */
 const char *mandel_last_error(void);
 

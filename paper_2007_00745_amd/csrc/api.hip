@@ -41,6 +41,7 @@ void clear_error() { g_err.clear(); }
 namespace {
 struct Workspace {
     unsigned long long *head = nullptr;
+    uint32_t *order_hist = nullptr;
 };
 std::mutex g_ws_mu;
 std::map<std::pair<int, hipStream_t>, Workspace> g_ws;
@@ -62,6 +63,25 @@ int workspace_head(hipStream_t s, unsigned long long **head)
         }
     }
     *head = w.head;
+    return MANDEL_OK;
+}
+
+int workspace_order(void *stream, uint32_t **hist)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return hip_fail(e, "hipGetDevice");
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    Workspace &w = g_ws[{dev, (hipStream_t)stream}];
+    if (!w.order_hist) {
+        e = hipMalloc((void **)&w.order_hist, sizeof(uint32_t) * 2 * MANDEL_ORDER_BUCKETS);
+        if (e != hipSuccess) {
+            w.order_hist = nullptr;
+            return fail(MANDEL_ENOMEM, "hipMalloc(order workspace): %s", hipGetErrorString(e));
+        }
+    }
+    *hist = w.order_hist;
     return MANDEL_OK;
 }
 

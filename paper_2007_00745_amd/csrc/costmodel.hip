@@ -1,0 +1,487 @@
+// Tile ordering kernels for gfx950: probe features, the FP32 tile cost model
+// (inference, and training by minibatch Adam), and the descending bucket
+// order.  The order only decides when each tile is rendered; counts are
+// unaffected (pixels are independent, paper Sec. II-A).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+
+#include "costmodel.h"
+#include "mandel.h"
+#include "mandel_internal.h"
+
+#pragma clang fp contract(off)
+
+namespace mandel {
+
+namespace {
+
+constexpr int NF = MANDEL_FEATURES;   // 68
+constexpr int NH = MANDEL_HIDDEN;     // 64
+constexpr int OFF_MU = 0;
+constexpr int OFF_ISD = NF;
+constexpr int OFF_W1 = MANDEL_MLP_NORM;           // [NH][NF]
+constexpr int OFF_B1 = OFF_W1 + NH * NF;
+constexpr int OFF_W2 = OFF_B1 + NH;               // [NH][NH]
+constexpr int OFF_B2 = OFF_W2 + NH * NH;
+constexpr int OFF_W3 = OFF_B2 + NH;
+constexpr int OFF_B3 = OFF_W3 + NH;
+static_assert(OFF_B3 + 1 == MANDEL_MLP_PARAMS, "parameter layout");
+constexpr int NTRAIN = MANDEL_MLP_PARAMS - MANDEL_MLP_NORM; // 8641
+
+__device__ __forceinline__ int32_t find_view_b(const ViewDesc *views, int32_t nviews, int64_t t)
+{
+    int32_t lo = 0, hi = nviews - 1;
+    while (lo < hi) {
+        int32_t mid = (lo + hi + 1) >> 1;
+        if (views[mid].tile_off <= t)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+// ---- probe features: one wavefront per tile, one probe pixel per lane ------
+__global__ void __launch_bounds__(256) features_kernel(const ViewDesc *views, int32_t nviews,
+                                                       int64_t ntiles, int32_t tile_w,
+                                                       int32_t tile_h, int32_t probe_cap,
+                                                       float *feat)
+{
+    const int64_t t = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x / 64);
+    if (t >= ntiles)
+        return;
+    const int lane = threadIdx.x & 63;
+    const int32_t v = find_view_b(views, nviews, t);
+    const ViewDesc vd = views[v];
+    const int64_t lt = t - vd.tile_off;
+    const int32_t ty = (int32_t)(lt / vd.tiles_x);
+    const int32_t tx = (int32_t)(lt - (int64_t)ty * vd.tiles_x);
+    const int32_t x0 = tx * tile_w, y0 = ty * tile_h;
+    const int32_t w = vd.n - x0 < tile_w ? vd.n - x0 : tile_w;
+    const int32_t h = vd.m - y0 < tile_h ? vd.m - y0 : tile_h;
+    const int32_t r = lane >> 3, k = lane & 7;
+    // probe pixel: column x0 + floor((k + 0.5) w / 8), row y0 + floor((r + 0.5) h / 8)
+    const int32_t j = x0 + (int32_t)(((int64_t)(2 * k + 1) * w) / 16);
+    const int32_t i = y0 + (int32_t)(((int64_t)(2 * r + 1) * h) / 16);
+    const double offx = ((double)j + 0.5) - 0.5 * (double)vd.n;
+    const double offy = ((double)i + 0.5) - 0.5 * (double)vd.m;
+    const double px = offx * vd.dx;
+    const double py = offy * vd.dy;
+    const double cx = vd.cx0 + px;
+    const double cy = vd.cy0 + py;
+    const int32_t cap = vd.max_iter < probe_cap ? vd.max_iter : probe_cap;
+    double x = 0.0, y = 0.0;
+    int32_t cnt = cap;
+    for (int32_t it = 1; it <= cap; ++it) {
+        const double xx = x * x;
+        const double yy = y * y;
+        const double tt = x * y;
+        x = (xx - yy) + cx;
+        y = __builtin_fma(2.0, tt, cy);
+        if (x * x + y * y > vd.R2) {
+            cnt = it;
+            break;
+        }
+    }
+    float *f = feat + t * NF;
+    f[4 + lane] = logf(1.0f + (float)cnt) / logf(1.0f + (float)cap);
+    if (lane < 4) {
+        float val;
+        if (lane == 0)
+            val = (float)(vd.cx0 + (((double)x0 + 0.5 * (double)w) - 0.5 * (double)vd.n) * vd.dx);
+        else if (lane == 1)
+            val = (float)(vd.cy0 + (((double)y0 + 0.5 * (double)h) - 0.5 * (double)vd.m) * vd.dy);
+        else if (lane == 2)
+            val = (float)log10((double)w * vd.dx);
+        else
+            val = logf((float)vd.max_iter);
+        f[lane] = val;
+    }
+}
+
+// ---- probe-sum heuristic key: ln(1 + sum of the (capped) probe counts) ------
+__global__ void probe_key_kernel(const float *feat, int64_t n, float *keys)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n)
+        return;
+    const float *f = feat + t * NF;
+    const float cap = fminf(expf(f[3]), 128.0f);
+    const float L = logf(1.0f + cap);
+    float s = 0.0f;
+    for (int k = 0; k < 64; ++k)
+        s += expf(f[4 + k] * L) - 1.0f;
+    keys[t] = logf(1.0f + s);
+}
+
+// ---- MLP inference: one row per thread, parameters staged in LDS -----------
+__global__ void __launch_bounds__(256) mlp_forward_kernel(const float *params, const float *x,
+                                                          int64_t n, float *y)
+{
+    __shared__ float P[MANDEL_MLP_PARAMS];
+    for (int q = threadIdx.x; q < MANDEL_MLP_PARAMS; q += blockDim.x)
+        P[q] = params[q];
+    __syncthreads();
+    const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (row >= n)
+        return;
+    const float *xr = x + row * NF;
+    float h[NH];
+#pragma unroll
+    for (int o = 0; o < NH; ++o)
+        h[o] = P[OFF_B1 + o];
+    for (int i = 0; i < NF; ++i) {
+        const float xi = (xr[i] - P[OFF_MU + i]) * P[OFF_ISD + i];
+#pragma unroll
+        for (int o = 0; o < NH; ++o)
+            h[o] += P[OFF_W1 + o * NF + i] * xi;
+    }
+#pragma unroll
+    for (int o = 0; o < NH; ++o)
+        h[o] = fmaxf(h[o], 0.0f);
+    float out = P[OFF_B3];
+    for (int o = 0; o < NH; ++o) {
+        float a = P[OFF_B2 + o];
+#pragma unroll
+        for (int i = 0; i < NH; ++i)
+            a += P[OFF_W2 + o * NH + i] * h[i];
+        out += P[OFF_W3 + o] * fmaxf(a, 0.0f);
+    }
+    y[row] = out;
+}
+
+// ---- MLP training ------------------------------------------------------------
+// work layout (floats): A1[B][64] | A2[B][64] | gy[B] | err[B] | gA1[B][64] | gA2[B][64]
+__global__ void __launch_bounds__(256) train_forward_kernel(const float *params, const float *x,
+                                                            const float *target,
+                                                            const int32_t *idx, int32_t B,
+                                                            float *work)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B)
+        return;
+    float *A1 = work, *A2 = work + (size_t)B * NH, *gy = work + (size_t)2 * B * NH;
+    float *err = gy + B;
+    const int64_t row = idx[b];
+    const float *xr = x + row * NF;
+    float h[NH];
+#pragma unroll
+    for (int o = 0; o < NH; ++o)
+        h[o] = params[OFF_B1 + o];
+    for (int i = 0; i < NF; ++i) {
+        const float xi = (xr[i] - params[OFF_MU + i]) * params[OFF_ISD + i];
+#pragma unroll
+        for (int o = 0; o < NH; ++o)
+            h[o] += params[OFF_W1 + o * NF + i] * xi;
+    }
+#pragma unroll
+    for (int o = 0; o < NH; ++o) {
+        A1[(size_t)b * NH + o] = h[o];
+        h[o] = fmaxf(h[o], 0.0f);
+    }
+    float out = params[OFF_B3];
+    for (int o = 0; o < NH; ++o) {
+        float a = params[OFF_B2 + o];
+#pragma unroll
+        for (int i = 0; i < NH; ++i)
+            a += params[OFF_W2 + o * NH + i] * h[i];
+        A2[(size_t)b * NH + o] = a;
+        out += params[OFF_W3 + o] * fmaxf(a, 0.0f);
+    }
+    const float e = out - target[row];
+    const float g = 2.0f * e / (float)B;
+    gy[b] = g;
+    err[b] = e * e;
+    float *gA2 = work + (size_t)3 * B * NH + 2 * (size_t)B;
+    for (int o = 0; o < NH; ++o)
+        gA2[(size_t)b * NH + o] = A2[(size_t)b * NH + o] > 0.0f ? g * params[OFF_W3 + o] : 0.0f;
+}
+
+// gA1[b][i] = relu'(A1[b][i]) * sum_o gA2[b][o] W2[o][i],  gA2[b][o] = gy[b] w3[o] relu'(A2[b][o])
+__global__ void __launch_bounds__(256) train_hidden_kernel(const float *params, int32_t B,
+                                                           float *work)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= (int64_t)B * NH)
+        return;
+    const int b = (int)(q / NH), i = (int)(q % NH);
+    const float *A1 = work;
+    float *gA1 = work + (size_t)2 * B * NH + 2 * (size_t)B;
+    const float *gA2 = gA1 + (size_t)B * NH;
+    float s = 0.0f;
+    for (int o = 0; o < NH; ++o)
+        s += gA2[(size_t)b * NH + o] * params[OFF_W2 + o * NH + i];
+    gA1[q] = A1[q] > 0.0f ? s : 0.0f;
+}
+
+// One thread per trainable parameter: its gradient (sum over the minibatch),
+// then the Adam update.
+__global__ void __launch_bounds__(256) train_grad_adam_kernel(float *params, float *m, float *v,
+                                                              const float *x, const int32_t *idx,
+                                                              int32_t B, const float *work,
+                                                              float lr, float bc1, float bc2)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= NTRAIN)
+        return;
+    const float *A1 = work, *A2 = work + (size_t)B * NH, *gy = work + (size_t)2 * B * NH;
+    const float *gA1 = work + (size_t)2 * B * NH + 2 * (size_t)B;
+    const float *gA2 = gA1 + (size_t)B * NH;
+    const int p = MANDEL_MLP_NORM + j;
+    float g = 0.0f;
+    if (p < OFF_B1) { // W1[o][i]
+        const int o = (p - OFF_W1) / NF, i = (p - OFF_W1) % NF;
+        const float mu = params[OFF_MU + i], isd = params[OFF_ISD + i];
+        for (int b = 0; b < B; ++b) {
+            const float xi = (x[(int64_t)idx[b] * NF + i] - mu) * isd;
+            g += gA1[(size_t)b * NH + o] * xi;
+        }
+    } else if (p < OFF_W2) { // b1[o]
+        const int o = p - OFF_B1;
+        for (int b = 0; b < B; ++b)
+            g += gA1[(size_t)b * NH + o];
+    } else if (p < OFF_B2) { // W2[o][i]
+        const int o = (p - OFF_W2) / NH, i = (p - OFF_W2) % NH;
+        for (int b = 0; b < B; ++b)
+            g += gA2[(size_t)b * NH + o] * fmaxf(A1[(size_t)b * NH + i], 0.0f);
+    } else if (p < OFF_W3) { // b2[o]
+        const int o = p - OFF_B2;
+        for (int b = 0; b < B; ++b)
+            g += gA2[(size_t)b * NH + o];
+    } else if (p < OFF_B3) { // w3[o]
+        const int o = p - OFF_W3;
+        for (int b = 0; b < B; ++b)
+            g += gy[b] * fmaxf(A2[(size_t)b * NH + o], 0.0f);
+    } else { // b3
+        for (int b = 0; b < B; ++b)
+            g += gy[b];
+    }
+    // Adam (Kingma & Ba): moments, bias correction, step.  The gradients read
+    // only saved activations and the (untrained) standardisation, never a
+    // parameter that this launch updates.
+    const float mj = 0.9f * m[p] + 0.1f * g;
+    const float vj = 0.999f * v[p] + 0.001f * g * g;
+    m[p] = mj;
+    v[p] = vj;
+    const float mh = mj / bc1;
+    const float vh = vj / bc2;
+    params[p] -= lr * mh / (sqrtf(vh) + 1e-8f);
+}
+
+__global__ void __launch_bounds__(256) train_loss_kernel(int32_t B, const float *work, float *loss)
+{
+    __shared__ float red[256];
+    const float *err = work + (size_t)2 * B * NH + B;
+    float s = 0.0f;
+    for (int b = threadIdx.x; b < B; b += blockDim.x)
+        s += err[b];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        *loss = red[0] / (float)B;
+}
+
+// ---- descending bucket order ---------------------------------------------------
+constexpr int NB = MANDEL_ORDER_BUCKETS;
+
+__device__ __forceinline__ int bucket_of(float key)
+{
+    if (!(key == key))
+        return NB - 1; // NaN: last
+    // NB - 1 buckets for numbers (out-of-range keys clamp to the end ones), the
+    // last bucket only for NaN
+    const float u = (MANDEL_ORDER_KEY_HI - key) * ((float)(NB - 1) / (MANDEL_ORDER_KEY_HI - MANDEL_ORDER_KEY_LO));
+    int b = (int)floorf(fminf(fmaxf(u, 0.0f), (float)(NB - 2)));
+    return b;
+}
+
+__global__ void zero_u32_kernel(uint32_t *p, int n)
+{
+    for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x)
+        p[q] = 0u;
+}
+
+__global__ void __launch_bounds__(1024) hist_kernel(const float *keys, int64_t n, uint32_t *hist)
+{
+    __shared__ uint32_t h[NB];
+    for (int q = threadIdx.x; q < NB; q += blockDim.x)
+        h[q] = 0u;
+    __syncthreads();
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n;
+         t += (int64_t)gridDim.x * blockDim.x)
+        atomicAdd(&h[bucket_of(keys[t])], 1u);
+    __syncthreads();
+    for (int q = threadIdx.x; q < NB; q += blockDim.x)
+        if (h[q])
+            atomicAdd(&hist[q], h[q]);
+}
+
+// exclusive scan of hist[0..NB) into cursor[0..NB) (one block of 1024 threads)
+__global__ void __launch_bounds__(1024) scan_kernel(const uint32_t *hist, uint32_t *cursor)
+{
+    __shared__ uint32_t part[1024];
+    constexpr int PER = NB / 1024;
+    const int t = threadIdx.x;
+    uint32_t loc[PER];
+    uint32_t s = 0;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        loc[k] = s;
+        s += hist[t * PER + k];
+    }
+    part[t] = s;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const uint32_t add = t >= off ? part[t - off] : 0u;
+        __syncthreads();
+        part[t] += add;
+        __syncthreads();
+    }
+    const uint32_t base = part[t] - s; // exclusive prefix of this thread's chunk
+#pragma unroll
+    for (int k = 0; k < PER; ++k)
+        cursor[t * PER + k] = base + loc[k];
+}
+
+__global__ void scatter_kernel(const float *keys, int64_t n, uint32_t *cursor, int32_t *perm)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n)
+        return;
+    const uint32_t pos = atomicAdd(&cursor[bucket_of(keys[t])], 1u);
+    perm[pos] = (int32_t)t;
+}
+
+unsigned blocks_for(int64_t n, int threads, int64_t cap = 1 << 30)
+{
+    int64_t b = (n + threads - 1) / threads;
+    if (b < 1)
+        b = 1;
+    if (b > cap)
+        b = cap;
+    return (unsigned)b;
+}
+
+} // namespace
+
+hipError_t launch_features(const ViewDesc *views, int32_t nviews, int64_t ntiles, int32_t tile_w,
+                           int32_t tile_h, int32_t probe_cap, float *feat, hipStream_t s)
+{
+    hipLaunchKernelGGL(features_kernel, dim3(blocks_for(ntiles, 4)), dim3(256), 0, s, views,
+                       nviews, ntiles, tile_w, tile_h, probe_cap, feat);
+    return hipGetLastError();
+}
+
+hipError_t launch_probe_key(const float *feat, int64_t n, float *keys, hipStream_t s)
+{
+    hipLaunchKernelGGL(probe_key_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, feat, n,
+                       keys);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_forward(const float *params, const float *x, int64_t n, float *y,
+                              hipStream_t s)
+{
+    hipLaunchKernelGGL(mlp_forward_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, params, x,
+                       n, y);
+    return hipGetLastError();
+}
+
+hipError_t launch_order_desc(const float *keys, int64_t n, int32_t *perm, uint32_t *hist,
+                             hipStream_t s)
+{
+    hipLaunchKernelGGL(zero_u32_kernel, dim3(8), dim3(1024), 0, s, hist, 2 * NB);
+    hipLaunchKernelGGL(hist_kernel, dim3(blocks_for(n, 1024, 256)), dim3(1024), 0, s, keys, n,
+                       hist);
+    hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, s, hist, hist + NB);
+    hipLaunchKernelGGL(scatter_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, keys, n,
+                       hist + NB, perm);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_train_step(float *params, float *m, float *v, int32_t t, const float *x,
+                                 const float *target, const int32_t *idx, int32_t B, float lr,
+                                 float *loss, float *work, hipStream_t s)
+{
+    const double bc1 = 1.0 - std::pow(0.9, (double)t);
+    const double bc2 = 1.0 - std::pow(0.999, (double)t);
+    hipLaunchKernelGGL(train_forward_kernel, dim3(blocks_for(B, 256)), dim3(256), 0, s, params,
+                       x, target, idx, B, work);
+    hipLaunchKernelGGL(train_hidden_kernel, dim3(blocks_for((int64_t)B * NH, 256)), dim3(256), 0,
+                       s, params, B, work);
+    if (loss)
+        hipLaunchKernelGGL(train_loss_kernel, dim3(1), dim3(256), 0, s, B, work, loss);
+    hipLaunchKernelGGL(train_grad_adam_kernel, dim3(blocks_for(NTRAIN, 256)), dim3(256), 0, s,
+                       params, m, v, x, idx, B, work, lr, (float)bc1, (float)bc2);
+    return hipGetLastError();
+}
+
+} // namespace mandel
+
+using namespace mandel;
+
+extern "C" {
+
+int mandel_mlp_forward(const float *params, const float *x, int64_t n, float *y, void *stream)
+{
+    clear_error();
+    if (n < 0)
+        return fail(MANDEL_EINVAL, "negative n");
+    if (n == 0)
+        return MANDEL_OK;
+    if (!params || !x || !y)
+        return fail(MANDEL_EINVAL, "null pointer");
+    hipError_t e = launch_mlp_forward(params, x, n, y, (hipStream_t)stream);
+    return e == hipSuccess ? MANDEL_OK : hip_fail(e, "mlp forward launch");
+}
+
+int64_t mandel_mlp_work_floats(int32_t batch)
+{
+    if (batch < 1)
+        return 0;
+    return (int64_t)batch * (4 * NH + 2);
+}
+
+int mandel_mlp_train_step(float *params, float *adam_m, float *adam_v, int32_t t, const float *x,
+                          const float *target, const int32_t *idx, int32_t batch, float lr,
+                          float *loss, float *work, void *stream)
+{
+    clear_error();
+    if (!params || !adam_m || !adam_v || !x || !target || !idx || !work)
+        return fail(MANDEL_EINVAL, "null pointer");
+    if (batch < 1 || batch > 4096)
+        return fail(MANDEL_EINVAL, "batch=%d outside [1, 4096]", batch);
+    if (t < 1)
+        return fail(MANDEL_EINVAL, "Adam step t=%d must be >= 1", t);
+    if (!(lr > 0.0f) || !std::isfinite(lr))
+        return fail(MANDEL_EINVAL, "lr must be finite and > 0");
+    hipError_t e = launch_mlp_train_step(params, adam_m, adam_v, t, x, target, idx, batch, lr,
+                                         loss, work, (hipStream_t)stream);
+    return e == hipSuccess ? MANDEL_OK : hip_fail(e, "mlp train launch");
+}
+
+int mandel_order_desc(const float *keys, int64_t n, int32_t *perm, void *stream)
+{
+    clear_error();
+    if (n < 0 || n >= ((int64_t)1 << 31))
+        return fail(MANDEL_EINVAL, "n=%lld outside [0, 2^31)", (long long)n);
+    if (n == 0)
+        return MANDEL_OK;
+    if (!keys || !perm)
+        return fail(MANDEL_EINVAL, "null pointer");
+    uint32_t *hist = nullptr;
+    int rc = workspace_order(stream, &hist);
+    if (rc)
+        return rc;
+    hipError_t e = launch_order_desc(keys, n, perm, hist, (hipStream_t)stream);
+    return e == hipSuccess ? MANDEL_OK : hip_fail(e, "order launch");
+}
+
+} // extern "C"

@@ -12,6 +12,7 @@ int fail(int code, const char *fmt, ...);
 int hip_fail(hipError_t e, const char *what);
 void clear_error();
 int workspace_head(hipStream_t s, unsigned long long **head);
+int workspace_order(void *stream, uint32_t **hist);
 int device_cus(int *cus);
 int64_t tile_count(int32_t m, int32_t n, int32_t tw, int32_t th);
 int make_view(const mandel_window *w, int32_t m, int32_t n, int32_t max_iter, double R,

@@ -1,0 +1,357 @@
+// Batch plans: many views rendered by one persistent launch over one flat tile
+// space, optionally through a captured hipGraph, in FCFS, caller-given or
+// predicted-longest-first order.  The operations are specified in
+// include/mandel.h.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "costmodel.h"
+#include "mandel.h"
+#include "mandel_internal.h"
+#include "render_kernels.h"
+
+using namespace mandel;
+
+namespace {
+
+struct GraphEntry {
+    int32_t *out;
+    int32_t mode;
+    const int32_t *order;
+    const float *mlp;
+    int64_t *tile_cost;
+    uint64_t *stats;
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+};
+
+} // namespace
+
+struct mandel_plan {
+    int device = 0;
+    std::vector<ViewDesc> views;
+    mandel_tuning tune{};
+    int64_t ntiles = 0;
+    int64_t npixels = 0;
+    ViewDesc *d_views = nullptr;
+    unsigned long long *d_head = nullptr;
+    // buffers of the ordered modes (allocated on first use)
+    float *d_feat = nullptr;
+    float *d_keys = nullptr;
+    int32_t *d_perm = nullptr;
+    uint32_t *d_hist = nullptr;
+    hipStream_t capture = nullptr;
+    std::vector<GraphEntry> graphs;
+};
+
+
+namespace {
+
+int fill_tuning(const mandel_tuning *t, mandel_tuning *o)
+{
+    mandel_tuning d;
+    std::memset(&d, 0, sizeof d);
+    if (t)
+        d = *t;
+    mandel_sched s;
+    std::memset(&s, 0, sizeof s);
+    s.policy = MANDEL_FCFS_TILES;
+    s.tile_w = d.tile_w;
+    s.tile_h = d.tile_h;
+    s.grain = d.grain;
+    s.waves_per_group = d.waves_per_group;
+    s.block_iters = d.block_iters;
+    s.young_iters = d.young_iters;
+    s.workers = d.groups;
+    mandel_sched c;
+    int rc = check_sched(&s, &c);
+    if (rc)
+        return rc;
+    d.tile_w = c.tile_w;
+    d.tile_h = c.tile_h;
+    d.grain = c.grain;
+    d.waves_per_group = c.waves_per_group;
+    d.block_iters = c.block_iters;
+    d.young_iters = c.young_iters;
+    d.groups = c.workers;
+    *o = d;
+    return MANDEL_OK;
+}
+
+int ensure_order_buffers(mandel_plan *p, bool need_feat)
+{
+    hipError_t e;
+    if (!p->d_keys) {
+        e = hipMalloc((void **)&p->d_keys, sizeof(float) * (size_t)(p->ntiles > 0 ? p->ntiles : 1));
+        if (e != hipSuccess)
+            return fail(MANDEL_ENOMEM, "hipMalloc(keys): %s", hipGetErrorString(e));
+    }
+    if (!p->d_perm) {
+        e = hipMalloc((void **)&p->d_perm, sizeof(int32_t) * (size_t)(p->ntiles > 0 ? p->ntiles : 1));
+        if (e != hipSuccess)
+            return fail(MANDEL_ENOMEM, "hipMalloc(perm): %s", hipGetErrorString(e));
+    }
+    if (!p->d_hist) {
+        e = hipMalloc((void **)&p->d_hist, sizeof(uint32_t) * 2 * MANDEL_ORDER_BUCKETS);
+        if (e != hipSuccess)
+            return fail(MANDEL_ENOMEM, "hipMalloc(order scratch): %s", hipGetErrorString(e));
+    }
+    if (need_feat && !p->d_feat) {
+        e = hipMalloc((void **)&p->d_feat,
+                      sizeof(float) * MANDEL_FEATURES * (size_t)(p->ntiles > 0 ? p->ntiles : 1));
+        if (e != hipSuccess)
+            return fail(MANDEL_ENOMEM, "hipMalloc(features): %s", hipGetErrorString(e));
+    }
+    return MANDEL_OK;
+}
+
+// Enqueues the whole launch sequence of one plan launch on stream s.
+int enqueue(mandel_plan *p, int32_t *out, const mandel_launch &la, hipStream_t s)
+{
+    hipError_t e;
+    const int32_t *order = nullptr;
+    int policy = POLICY_FCFS_TILES;
+    if (la.mode == MANDEL_PLAN_ORDERED) {
+        order = la.order;
+        policy = POLICY_ORDERED_TILES;
+    } else if (la.mode == MANDEL_PLAN_PROBE_LPT || la.mode == MANDEL_PLAN_LEARNED_LPT) {
+        e = launch_features(p->d_views, (int32_t)p->views.size(), p->ntiles, p->tune.tile_w,
+                            p->tune.tile_h, 128, p->d_feat, s);
+        if (e != hipSuccess)
+            return hip_fail(e, "features launch");
+        if (la.mode == MANDEL_PLAN_PROBE_LPT)
+            e = launch_probe_key(p->d_feat, p->ntiles, p->d_keys, s);
+        else
+            e = launch_mlp_forward(la.mlp, p->d_feat, p->ntiles, p->d_keys, s);
+        if (e != hipSuccess)
+            return hip_fail(e, "key launch");
+        e = launch_order_desc(p->d_keys, p->ntiles, p->d_perm, p->d_hist, s);
+        if (e != hipSuccess)
+            return hip_fail(e, "order launch");
+        order = p->d_perm;
+        policy = POLICY_ORDERED_TILES;
+    }
+
+    RenderArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.v0 = p->views[0];
+    a.views = p->d_views;
+    a.nviews = (int32_t)p->views.size();
+    a.tile_w = p->tune.tile_w;
+    a.tile_h = p->tune.tile_h;
+    a.grain = p->tune.grain;
+    a.ntiles = p->ntiles;
+    a.block_iters = p->tune.block_iters;
+    a.young_iters = p->tune.young_iters;
+    a.out = out;
+    a.head = p->d_head;
+    a.order = order;
+    a.tile_cost = la.tile_cost;
+    a.claims = nullptr;
+    a.stats = la.stats;
+
+    mandel_sched sc;
+    std::memset(&sc, 0, sizeof sc);
+    sc.policy = policy;
+    sc.waves_per_group = p->tune.waves_per_group;
+    sc.workers = p->tune.groups;
+    dim3 grid, block;
+    int rc = tile_grid(sc, true, p->ntiles, &grid, &block);
+    if (rc)
+        return rc;
+    e = launch_clear(p->d_head, la.tile_cost, nullptr, la.tile_cost ? p->ntiles : 0, s);
+    if (e != hipSuccess)
+        return hip_fail(e, "clear launch");
+    e = launch_render(a, policy, true, true, grid, block, s);
+    if (e != hipSuccess)
+        return hip_fail(e, "render launch");
+    return MANDEL_OK;
+}
+
+} // namespace
+
+extern "C" {
+
+int mandel_plan_create(const mandel_view *views, int32_t nviews, const mandel_tuning *tuning,
+                       mandel_plan **plan)
+{
+    clear_error();
+    if (!plan)
+        return fail(MANDEL_EINVAL, "plan is NULL");
+    *plan = nullptr;
+    if (!views || nviews < 1 || nviews > (1 << 24))
+        return fail(MANDEL_EINVAL, "need 1 <= nviews <= 2^24 and a view array");
+    mandel_tuning tu;
+    int rc = fill_tuning(tuning, &tu);
+    if (rc)
+        return rc;
+    mandel_plan *p = new (std::nothrow) mandel_plan();
+    if (!p)
+        return fail(MANDEL_ENOMEM, "host allocation failed");
+    p->tune = tu;
+    p->views.resize((size_t)nviews);
+    int64_t toff = 0, npx = 0;
+    for (int32_t k = 0; k < nviews; ++k) {
+        const mandel_view &v = views[k];
+        rc = make_view(&v.w, v.m, v.n, v.max_iter, v.R, tu.tile_w, tu.tile_h, &p->views[k]);
+        if (rc) {
+            delete p;
+            return fail(rc, "view %d: %s", k, mandel_last_error());
+        }
+        if (v.out_offset < 0) {
+            delete p;
+            return fail(MANDEL_EINVAL, "view %d: negative out_offset", k);
+        }
+        p->views[k].out_off = v.out_offset;
+        p->views[k].tile_off = toff;
+        toff += tile_count(v.m, v.n, tu.tile_w, tu.tile_h);
+        npx += (int64_t)v.m * v.n;
+    }
+    if (toff >= ((int64_t)1 << 31)) {
+        delete p;
+        return fail(MANDEL_EINVAL, "plan has %lld tiles (limit 2^31 - 1)", (long long)toff);
+    }
+    p->ntiles = toff;
+    p->npixels = npx;
+    hipError_t e = hipGetDevice(&p->device);
+    if (e == hipSuccess)
+        e = hipMalloc((void **)&p->d_views, sizeof(ViewDesc) * (size_t)nviews);
+    if (e == hipSuccess)
+        e = hipMemcpy(p->d_views, p->views.data(), sizeof(ViewDesc) * (size_t)nviews,
+                      hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMalloc((void **)&p->d_head, 256);
+    if (e == hipSuccess)
+        e = hipStreamCreateWithFlags(&p->capture, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        mandel_plan_destroy(p);
+        return hip_fail(e, "plan allocation");
+    }
+    *plan = p;
+    return MANDEL_OK;
+}
+
+int mandel_plan_info(const mandel_plan *p, int64_t *ntiles, int64_t *npixels, mandel_tuning *t)
+{
+    clear_error();
+    if (!p)
+        return fail(MANDEL_EINVAL, "plan is NULL");
+    if (ntiles)
+        *ntiles = p->ntiles;
+    if (npixels)
+        *npixels = p->npixels;
+    if (t)
+        *t = p->tune;
+    return MANDEL_OK;
+}
+
+int mandel_plan_launch(mandel_plan *p, int32_t *out, const mandel_launch *args, void *stream)
+{
+    clear_error();
+    if (!p)
+        return fail(MANDEL_EINVAL, "plan is NULL");
+    mandel_launch la;
+    std::memset(&la, 0, sizeof la);
+    if (args)
+        la = *args;
+    if (la.mode < MANDEL_PLAN_FCFS || la.mode > MANDEL_PLAN_LEARNED_LPT)
+        return fail(MANDEL_EINVAL, "unknown plan mode %d", la.mode);
+    if (la.mode == MANDEL_PLAN_ORDERED && !la.order)
+        return fail(MANDEL_EINVAL, "ORDERED needs an order array");
+    if (la.mode == MANDEL_PLAN_LEARNED_LPT && !la.mlp)
+        return fail(MANDEL_EINVAL, "LEARNED_LPT needs model parameters");
+    if (p->ntiles == 0)
+        return MANDEL_OK;
+    if (!out)
+        return fail(MANDEL_EINVAL, "out_base is NULL");
+    if (la.mode >= MANDEL_PLAN_PROBE_LPT) {
+        int rc = ensure_order_buffers(p, true);
+        if (rc)
+            return rc;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    if (!la.use_graph)
+        return enqueue(p, out, la, s);
+
+    for (const GraphEntry &g : p->graphs) {
+        if (g.out == out && g.mode == la.mode && g.order == la.order && g.mlp == la.mlp &&
+            g.tile_cost == la.tile_cost && g.stats == la.stats) {
+            hipError_t e = hipGraphLaunch(g.exec, s);
+            return e == hipSuccess ? MANDEL_OK : hip_fail(e, "hipGraphLaunch");
+        }
+    }
+    GraphEntry g;
+    g.out = out;
+    g.mode = la.mode;
+    g.order = la.order;
+    g.mlp = la.mlp;
+    g.tile_cost = la.tile_cost;
+    g.stats = la.stats;
+    g.graph = nullptr;
+    g.exec = nullptr;
+    hipError_t e = hipStreamBeginCapture(p->capture, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess)
+        return hip_fail(e, "hipStreamBeginCapture");
+    int rc = enqueue(p, out, la, p->capture);
+    e = hipStreamEndCapture(p->capture, &g.graph);
+    if (rc)
+        return rc;
+    if (e != hipSuccess)
+        return hip_fail(e, "hipStreamEndCapture");
+    e = hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(g.graph);
+        return hip_fail(e, "hipGraphInstantiate");
+    }
+    p->graphs.push_back(g);
+    e = hipGraphLaunch(g.exec, s);
+    return e == hipSuccess ? MANDEL_OK : hip_fail(e, "hipGraphLaunch");
+}
+
+int mandel_plan_features(mandel_plan *p, float *feat, int32_t probe_cap, void *stream)
+{
+    clear_error();
+    if (!p)
+        return fail(MANDEL_EINVAL, "plan is NULL");
+    if (probe_cap == 0)
+        probe_cap = 128;
+    if (probe_cap < 1 || probe_cap > (1 << 20))
+        return fail(MANDEL_EINVAL, "probe_cap=%d outside [1, 2^20]", probe_cap);
+    if (p->ntiles == 0)
+        return MANDEL_OK;
+    if (!feat)
+        return fail(MANDEL_EINVAL, "feat is NULL");
+    hipError_t e = launch_features(p->d_views, (int32_t)p->views.size(), p->ntiles,
+                                   p->tune.tile_w, p->tune.tile_h, probe_cap, feat,
+                                   (hipStream_t)stream);
+    return e == hipSuccess ? MANDEL_OK : hip_fail(e, "features launch");
+}
+
+int mandel_plan_destroy(mandel_plan *p)
+{
+    clear_error();
+    if (!p)
+        return MANDEL_OK;
+    (void)hipDeviceSynchronize();
+    for (GraphEntry &g : p->graphs) {
+        if (g.exec)
+            (void)hipGraphExecDestroy(g.exec);
+        if (g.graph)
+            (void)hipGraphDestroy(g.graph);
+    }
+    if (p->capture)
+        (void)hipStreamDestroy(p->capture);
+    (void)hipFree(p->d_views);
+    (void)hipFree(p->d_head);
+    (void)hipFree(p->d_feat);
+    (void)hipFree(p->d_keys);
+    (void)hipFree(p->d_perm);
+    (void)hipFree(p->d_hist);
+    delete p;
+    return MANDEL_OK;
+}
+
+} // extern "C"

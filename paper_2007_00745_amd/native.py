@@ -46,6 +46,35 @@ class Sched(ctypes.Structure):
                 ("claims", ctypes.c_void_p), ("stats", ctypes.c_void_p)]
 
 
+class ViewC(ctypes.Structure):
+    _fields_ = [("w", Window), ("m", ctypes.c_int32), ("n", ctypes.c_int32),
+                ("max_iter", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("R", ctypes.c_double), ("out_offset", ctypes.c_int64)]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32),
+                ("grain", ctypes.c_int32), ("waves_per_group", ctypes.c_int32),
+                ("block_iters", ctypes.c_int32), ("young_iters", ctypes.c_int32),
+                ("groups", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+    def as_dict(self) -> dict:
+        return {k: int(getattr(self, k)) for k, _ in self._fields_ if k != "reserved"}
+
+
+class LaunchC(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int32), ("use_graph", ctypes.c_int32),
+                ("order", ctypes.c_void_p), ("mlp", ctypes.c_void_p),
+                ("tile_cost", ctypes.c_void_p), ("stats", ctypes.c_void_p)]
+
+
+PLAN_MODES = {"fcfs": 0, "ordered": 1, "probe": 2, "learned": 3}
+NFEAT = 68
+MLP_PARAMS = 8777
+MLP_NORM = 136
+ORDER_BUCKETS = 4096
+ORDER_KEY_LO, ORDER_KEY_HI = -2.0, 50.0
+
 _lock = threading.Lock()
 _lib = None
 
@@ -78,6 +107,26 @@ def lib() -> ctypes.CDLL:
         L.mandel_last_error.restype = ctypes.c_char_p
         L.mandel_version.argtypes = []
         L.mandel_version.restype = ctypes.c_char_p
+        L.mandel_plan_create.argtypes = [ctypes.POINTER(ViewC), i32, ctypes.POINTER(Tuning),
+                                         ctypes.POINTER(ctypes.c_void_p)]
+        L.mandel_plan_create.restype = ctypes.c_int
+        L.mandel_plan_info.argtypes = [P, ctypes.POINTER(i64), ctypes.POINTER(i64),
+                                       ctypes.POINTER(Tuning)]
+        L.mandel_plan_info.restype = ctypes.c_int
+        L.mandel_plan_launch.argtypes = [P, P, ctypes.POINTER(LaunchC), P]
+        L.mandel_plan_launch.restype = ctypes.c_int
+        L.mandel_plan_destroy.argtypes = [P]
+        L.mandel_plan_destroy.restype = ctypes.c_int
+        L.mandel_plan_features.argtypes = [P, P, i32, P]
+        L.mandel_plan_features.restype = ctypes.c_int
+        L.mandel_mlp_forward.argtypes = [P, P, i64, P, P]
+        L.mandel_mlp_forward.restype = ctypes.c_int
+        L.mandel_mlp_work_floats.argtypes = [i32]
+        L.mandel_mlp_work_floats.restype = i64
+        L.mandel_mlp_train_step.argtypes = [P, P, P, i32, P, P, P, i32, ctypes.c_float, P, P, P]
+        L.mandel_mlp_train_step.restype = ctypes.c_int
+        L.mandel_order_desc.argtypes = [P, i64, P, P]
+        L.mandel_order_desc.restype = ctypes.c_int
         _lib = L
         return L
 
@@ -144,3 +193,99 @@ def render_sched(window, m: int, n: int, max_iter: int, R: float, out=None, stre
     check(lib().mandel_render_sched(ctypes.byref(w), m, n, int(max_iter), float(R), _ptr(out),
                                     ctypes.byref(s), _stream(stream)))
     return out
+
+
+# ---- batches ----------------------------------------------------------------
+
+class Plan:
+    """A batch plan (mandel_plan_*): views rendered by one persistent launch."""
+
+    def __init__(self, views, tuning: dict | None = None, out_offsets=None):
+        n = len(views)
+        arr = (ViewC * n)()
+        offs = out_offsets
+        if offs is None:
+            offs, acc = [], 0
+            for v in views:
+                offs.append(acc)
+                acc += v.m * v.n
+        for k, v in enumerate(views):
+            arr[k] = ViewC(Window(*[float(t) for t in v.window]), int(v.m), int(v.n),
+                           int(v.max_iter), 0, float(v.R), int(offs[k]))
+        tu = Tuning(**(tuning or {}))
+        h = ctypes.c_void_p()
+        check(lib().mandel_plan_create(arr, n, ctypes.byref(tu), ctypes.byref(h)))
+        self._h = h
+        self.views = list(views)
+        self.out_offsets = list(offs)
+        nt, npx, t = ctypes.c_int64(), ctypes.c_int64(), Tuning()
+        check(lib().mandel_plan_info(h, ctypes.byref(nt), ctypes.byref(npx), ctypes.byref(t)))
+        self.ntiles, self.npixels, self.tuning = int(nt.value), int(npx.value), t.as_dict()
+
+    def out_size(self) -> int:
+        return max((o + v.m * v.n for o, v in zip(self.out_offsets, self.views)), default=0)
+
+    def launch(self, out, mode="fcfs", use_graph=False, order=None, mlp=None, tile_cost=None,
+               stats=None, stream=None):
+        la = LaunchC(PLAN_MODES[mode] if isinstance(mode, str) else int(mode), int(use_graph),
+                     _ptr(order), _ptr(mlp), _ptr(tile_cost), _ptr(stats))
+        check(lib().mandel_plan_launch(self._h, _ptr(out), ctypes.byref(la), _stream(stream)))
+        return out
+
+    def features(self, feat=None, probe_cap: int = 0, stream=None):
+        import torch
+        if feat is None:
+            feat = torch.empty((self.ntiles, NFEAT), dtype=torch.float32, device="cuda")
+        check(lib().mandel_plan_features(self._h, _ptr(feat), int(probe_cap), _stream(stream)))
+        return feat
+
+    def view_images(self, out):
+        """Split a packed output buffer into per-view (m, n) tensors."""
+        return [out[o:o + v.m * v.n].view(v.m, v.n) for o, v in zip(self.out_offsets, self.views)]
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().mandel_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---- cost model and ordering ----------------------------------------------------
+
+def mlp_forward(params, x, y=None, stream=None):
+    import torch
+    n = x.shape[0]
+    if y is None:
+        y = torch.empty(n, dtype=torch.float32, device=x.device)
+    check(lib().mandel_mlp_forward(_ptr(params), _ptr(x), n, _ptr(y), _stream(stream)))
+    return y
+
+
+def mlp_work_floats(batch: int) -> int:
+    return int(lib().mandel_mlp_work_floats(batch))
+
+
+def mlp_train_step(params, m, v, t: int, x, target, idx, lr: float, loss=None, work=None,
+                   stream=None):
+    import torch
+    B = idx.numel()
+    if work is None:
+        work = torch.empty(mlp_work_floats(B), dtype=torch.float32, device=x.device)
+    check(lib().mandel_mlp_train_step(_ptr(params), _ptr(m), _ptr(v), int(t), _ptr(x),
+                                      _ptr(target), _ptr(idx), B, float(lr), _ptr(loss),
+                                      _ptr(work), _stream(stream)))
+    return work
+
+
+def order_desc(keys, perm=None, stream=None):
+    import torch
+    n = keys.numel()
+    if perm is None:
+        perm = torch.empty(n, dtype=torch.int32, device=keys.device)
+    check(lib().mandel_order_desc(_ptr(keys), n, _ptr(perm), _stream(stream)))
+    return perm

@@ -1,0 +1,244 @@
+"""GPU tests of batch plans, graph replay, probe features, the FP32 cost model
+(inference and one training step) and the descending tile order.
+
+Counts are compared with the CPU oracle bit for bit (paper Sec. I, Eq. (1)-(2));
+the cost model is compared with the FP64 reference in oracle/mlp.py within
+FP32 tolerances (rtol 1e-3 / atol 1e-5 of the gradient scale)."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import mlp as mlp_ref
+from paper_2007_00745_amd import native, workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def _log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def small_batch():
+    views = workloads.c3_scaled(745, 64, scale=32)
+    views += [workloads.View((-0.5, 0.0, 0.01, 0.01), 0, 17, 100),   # empty view
+              workloads.View((0.3, 0.1, 0.1, 0.1), 1, 1, 50),
+              workloads.View(workloads.window_from_bounds(-2, 1, -1.2, 1.2, 33, 70), 33, 70, 300)]
+    want = [oracle.render(v.window, v.m, v.n, v.max_iter, v.R) for v in views]
+    return views, want
+
+
+def _check(plan, out, want):
+    imgs = plan.view_images(out.cpu())
+    for k, (g, w) in enumerate(zip(imgs, want)):
+        assert np.array_equal(g.numpy(), w), f"view {k}"
+
+
+def _params(seed, feat=None):
+    rng = np.random.default_rng(seed)
+    if feat is not None:
+        f = feat.cpu().double().numpy()
+        p = mlp_ref.init_params(rng, mu=f.mean(0), sd=f.std(0) + 1e-3)
+    else:
+        p = mlp_ref.init_params(rng, mu=rng.normal(size=68) * 0.1, sd=rng.uniform(0.5, 2, 68))
+    return p
+
+
+@pytest.mark.parametrize("tuning", [{}, dict(tile_w=32, tile_h=4, grain=3),
+                                    dict(tile_w=16, tile_h=16, waves_per_group=1, groups=37)])
+def test_plan_fcfs(small_batch, tuning):
+    views, want = small_batch
+    plan = native.Plan(views, tuning)
+    _log(f"plan {plan.ntiles} tiles {tuning}")
+    out = torch.full((plan.out_size(),), -1, dtype=torch.int32, device="cuda")
+    plan.launch(out)
+    torch.cuda.synchronize()
+    _check(plan, out, want)
+    plan.close()
+
+
+def test_plan_modes_and_graph_replays(small_batch):
+    views, want = small_batch
+    plan = native.Plan(views)
+    nt = plan.ntiles
+    feat = plan.features()
+    params = torch.tensor(_params(3, feat), dtype=torch.float32, device="cuda")
+    order = torch.tensor(np.random.default_rng(5).permutation(nt), dtype=torch.int32,
+                         device="cuda")
+    for mode in ("fcfs", "ordered", "probe", "learned"):
+        kw = dict(order=order) if mode == "ordered" else {}
+        if mode == "learned":
+            kw["mlp"] = params
+        out = torch.full((plan.out_size(),), -1, dtype=torch.int32, device="cuda")
+        _log(f"mode {mode} eager")
+        plan.launch(out, mode=mode, **kw)
+        torch.cuda.synchronize()
+        eager = out.clone()
+        _check(plan, eager, want)
+        gout = torch.full_like(out, -7)
+        for rep in range(3):
+            _log(f"mode {mode} graph replay {rep}")
+            gout.fill_(-7)                      # eager work between replays
+            torch.cuda.synchronize()
+            plan.launch(gout, mode=mode, use_graph=True, **kw)
+            torch.cuda.synchronize()
+            assert torch.equal(gout, eager), (mode, rep)
+    plan.close()
+
+
+def _tile_sums(views, imgs, tw, th):
+    sums = []
+    for v, img in zip(views, imgs):
+        if v.m == 0 or v.n == 0:
+            continue
+        ty, tx = -(-v.m // th), -(-v.n // tw)
+        pad = np.zeros((ty * th, tx * tw), dtype=np.int64)
+        pad[:v.m, :v.n] = img
+        sums.append(pad.reshape(ty, th, tx, tw).sum(axis=(1, 3)).ravel())
+    return np.concatenate(sums)
+
+
+def test_plan_tile_cost_and_stats(small_batch):
+    views, want = small_batch
+    plan = native.Plan(views, dict(tile_w=32, tile_h=8))
+    cost = torch.full((plan.ntiles,), -5, dtype=torch.int64, device="cuda")
+    stats = torch.zeros(4, dtype=torch.int64, device="cuda")
+    out = torch.empty((plan.out_size(),), dtype=torch.int32, device="cuda")
+    for use_graph in (False, True, True):
+        cost.fill_(-5)
+        stats.zero_()
+        plan.launch(out, tile_cost=cost, stats=stats, use_graph=use_graph)
+        torch.cuda.synchronize()
+        assert np.array_equal(cost.cpu().numpy(), _tile_sums(views, want, 32, 8))
+        st = stats.cpu().numpy()
+        assert st[1] == sum(int(w.sum()) for w in want) and st[3] == plan.ntiles
+    plan.close()
+
+
+def test_single_view_plan_equals_render():
+    v = workloads.c1()
+    plan = native.Plan([v])
+    out = torch.empty(v.m * v.n, dtype=torch.int32, device="cuda")
+    plan.launch(out, use_graph=True)
+    ref = native.render(v.window, v.m, v.n, v.max_iter, v.R)
+    torch.cuda.synchronize()
+    assert torch.equal(out.view(v.m, v.n), ref)
+    plan.close()
+
+
+def test_plan_rejects_bad_views():
+    bad = [workloads.View((0.0, 0.0, 0.0, 0.01), 4, 4, 10)]
+    with pytest.raises(native.MandelError):
+        native.Plan(bad)
+    with pytest.raises(native.MandelError):
+        native.Plan([workloads.View((0.0, 0.0, 0.01, 0.01), 4, 4, 0)])
+
+
+def test_features_probe_counts(small_batch):
+    views, _ = small_batch
+    tw, th = 64, 8
+    plan = native.Plan(views, dict(tile_w=tw, tile_h=th))
+    for cap_arg in (0, 7, 300):
+        feat = plan.features(probe_cap=cap_arg).cpu().double().numpy()
+        cap_req = 128 if cap_arg == 0 else cap_arg
+        t = 0
+        for v in views:
+            if v.m == 0 or v.n == 0:
+                continue
+            cap = min(v.max_iter, cap_req)
+            ty, tx = -(-v.m // th), -(-v.n // tw)
+            for a in range(ty):
+                for b in range(tx):
+                    x0, y0 = b * tw, a * th
+                    w, h = min(tw, v.n - x0), min(th, v.m - y0)
+                    cols = [x0 + ((2 * k + 1) * w) // 16 for k in range(8)]
+                    rows = [y0 + ((2 * r + 1) * h) // 16 for r in range(8)]
+                    idx = np.array([[i * v.n + j for j in cols] for i in rows]).ravel()
+                    ref = np.minimum(oracle.render_pixels(v.window, v.m, v.n, v.max_iter, v.R,
+                                                          idx), cap)
+                    got = np.rint(np.exp(feat[t, 4:] * np.log1p(cap)) - 1)
+                    assert np.array_equal(got.astype(np.int64), ref), (t, cap)
+                    cxw = v.window[0] + ((x0 + w / 2) - v.n / 2) * v.window[2]
+                    cyw = v.window[1] + ((y0 + h / 2) - v.m / 2) * v.window[3]
+                    assert np.isclose(feat[t, 0], cxw, rtol=1e-6, atol=1e-7)
+                    assert np.isclose(feat[t, 1], cyw, rtol=1e-6, atol=1e-7)
+                    assert np.isclose(feat[t, 2], np.log10(w * v.window[2]), atol=1e-5)
+                    assert np.isclose(feat[t, 3], np.log(v.max_iter), atol=1e-5)
+                    t += 1
+        assert t == plan.ntiles
+    plan.close()
+
+
+def test_mlp_forward_matches_fp64():
+    rng = np.random.default_rng(11)
+    p = _params(12)
+    x = rng.normal(size=(3001, 68)) * rng.uniform(0.5, 3, 68) + rng.normal(size=68)
+    y_ref = mlp_ref.forward(p, x)
+    y = native.mlp_forward(torch.tensor(p, dtype=torch.float32, device="cuda"),
+                           torch.tensor(x, dtype=torch.float32, device="cuda"))
+    torch.cuda.synchronize()
+    assert np.allclose(y.cpu().numpy(), y_ref, rtol=1e-3, atol=1e-4 * np.abs(y_ref).max())
+
+
+def test_mlp_train_step_matches_fp64():
+    rng = np.random.default_rng(21)
+    n, B = 2000, 512
+    x = rng.normal(size=(n, 68))
+    t = np.tanh(x[:, :5].sum(1)) * 4 + 10
+    p = _params(22)
+    dev = dict(dtype=torch.float32, device="cuda")
+    P = torch.tensor(p, **dev)
+    M = torch.zeros_like(P)
+    V = torch.zeros_like(P)
+    X = torch.tensor(x, **dev)
+    T = torch.tensor(t, **dev)
+    loss = torch.zeros(1, **dev)
+    m_ref = np.zeros_like(p)
+    v_ref = np.zeros_like(p)
+    for step in range(1, 4):
+        idx = rng.choice(n, B, replace=False)
+        I = torch.tensor(idx, dtype=torch.int32, device="cuda")
+        M_before = M.cpu().double().numpy()
+        # reference step from the GPU's own parameters, so errors do not accumulate
+        p_in = P.cpu().double().numpy()
+        native.mlp_train_step(P, M, V, step, X, T, I, 1e-3, loss=loss)
+        torch.cuda.synchronize()
+        L_ref, g_ref = mlp_ref.loss_and_grad(p_in, x[idx], t[idx])
+        assert np.isclose(loss.item(), L_ref, rtol=1e-4)
+        g_gpu = (M.cpu().double().numpy() - 0.9 * M_before) / 0.1
+        scale = np.abs(g_ref).max()
+        s = slice(136, None)
+        assert np.allclose(g_gpu[s], g_ref[s], rtol=1e-3, atol=1e-5 * scale)
+        assert np.array_equal(P.cpu().numpy()[:136], np.float32(p[:136]))
+        # where the gradient is well above FP32 noise, the Adam step agrees too
+        pr, mr, vr = mlp_ref.adam_step(p_in, M_before, V_before if step > 1 else np.zeros_like(p_in),
+                                       g_ref, step, 1e-3)
+        V_before = V.cpu().double().numpy()
+        big = np.abs(g_ref) > 1e-2 * scale
+        big[:136] = False
+        assert np.allclose(P.cpu().double().numpy()[big], pr[big], rtol=1e-4, atol=1e-6)
+
+
+def test_order_desc():
+    rng = np.random.default_rng(31)
+    for n in (1, 2, 1000, 131072, 2_621_440):
+        keys = rng.uniform(-3, 52, n).astype(np.float32)
+        if n > 10:
+            keys[rng.choice(n, 5, replace=False)] = np.nan
+        k = torch.tensor(keys, device="cuda")
+        perm = native.order_desc(k)
+        torch.cuda.synchronize()
+        pm = perm.cpu().numpy()
+        assert np.array_equal(np.sort(pm), np.arange(n))
+        kk = keys[pm]
+        nb = native.ORDER_BUCKETS
+        f32 = np.float32   # the kernel's bucket arithmetic, in float32
+        scale = f32(nb - 1) / (f32(native.ORDER_KEY_HI) - f32(native.ORDER_KEY_LO))
+        u = (f32(native.ORDER_KEY_HI) - kk) * scale
+        b = np.where(np.isnan(kk), nb - 1, np.floor(np.clip(np.nan_to_num(u, nan=0), 0, nb - 2)))
+        assert np.all(np.diff(b) >= 0)
+        if n > 10:
+            assert np.all(np.isnan(kk[-5:]))
