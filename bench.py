@@ -89,7 +89,7 @@ def main():
         step()
     torch.cuda.synchronize()
     sum_counts = int(out.sum(dtype=torch.int64).item())
-    stats = torch.zeros(4, dtype=torch.int64, device="cuda")
+    stats = torch.zeros(8, dtype=torch.int64, device="cuda")
     native.render_sched(view.window, view.m, view.n, view.max_iter, view.R, out=out,
                         stream=stream, stats=stats, **sched)
     torch.cuda.synchronize()

@@ -101,11 +101,18 @@ typedef struct mandel_sched {
     const int32_t *order;    /* device int32[ntiles], ORDERED_TILES only: a permutation */
     int64_t *tile_cost;      /* device int64[ntiles] or NULL: sum of counts per tile
                                 (tile policies; cleared by the call) */
-    int32_t *claims;         /* device int32[ntiles] or NULL: times each tile was
-                                claimed (tile policies; cleared by the call) */
-    uint64_t *stats;         /* device uint64[4] or NULL, accumulated (not cleared):
-                                [0] wavefront loop iterations, [1] sum of counts,
-                                [2] wavefronts that ran, [3] work items taken */
+    int32_t *claims;         /* NULL, or a log cleared by the call: tile policies,
+                                device int32[ntiles], times each tile was claimed;
+                                row policies, device int32[m], the sum of (worker + 1)
+                                over the takes of each row (a row taken once by
+                                worker r holds r + 1) */
+    uint64_t *stats;         /* device uint64[8] or NULL.  [0..3] accumulate over
+                                calls (never cleared): [0] wavefront loop iterations,
+                                [1] sum of counts, [2] wavefronts that ran, [3] work
+                                items taken.  [4..6] are set per call, in wall-clock
+                                ticks (hipDeviceAttributeWallClockRate): [4] first
+                                queue claim, [5] first claim that found the queue
+                                empty, [6] last wavefront exit (tile policies) */
 } mandel_sched;
 
 /*
@@ -183,7 +190,7 @@ typedef struct mandel_launch {
     const int32_t *order;    /* device int32[ntiles], ORDERED: a permutation of tile ids */
     const float *mlp;        /* device float[MANDEL_MLP_PARAMS], LEARNED_LPT: the cost model */
     int64_t *tile_cost;      /* device int64[ntiles] or NULL: sum of counts per tile */
-    uint64_t *stats;         /* device uint64[4] or NULL (as in mandel_sched) */
+    uint64_t *stats;         /* device uint64[8] or NULL (as in mandel_sched) */
 } mandel_launch;
 
 /*
@@ -265,6 +272,26 @@ int mandel_mlp_train_step(float *params, float *adam_m, float *adam_v, int32_t t
 #define MANDEL_ORDER_KEY_LO (-2.0f)
 #define MANDEL_ORDER_KEY_HI 50.0f
 int mandel_order_desc(const float *keys, int64_t n, int32_t *perm, void *stream);
+
+/* Sets the standardisation entries of params (mu, inv_sd; device) from the
+ * column means and standard deviations of feat (device float[n][68], n >= 1):
+ * inv_sd = 1 / max(sd, 1e-6).  The trained entries are not touched. */
+int mandel_mlp_set_norm(float *params, const float *feat, int64_t n, void *stream);
+
+/* Training targets: target[i] = ln(max(cost[i], 1)) for device int64 cost[n]. */
+int mandel_cost_targets(const int64_t *cost, int64_t n, float *target, void *stream);
+
+/*
+ * mandel_plan_autotune -- picks the plan tuning (tile shape, claim grain,
+ * waves per workgroup) for a batch by timing every candidate on a sample of
+ * the views (at most max_sample views, spread over the batch's range of
+ * pixels x max_iter), and caches the choice per device and batch signature.
+ * Synchronous: it allocates a scratch image, renders the sample several
+ * times on `stream` and waits.  best receives the chosen tuning; trials
+ * (host, may be NULL) receives how many candidate launches were timed.
+ */
+int mandel_plan_autotune(const mandel_view *views, int32_t nviews, int32_t max_sample,
+                         mandel_tuning *best, int32_t *trials, void *stream);
 
 /* Text of the last error on this thread ("" if none). */
 const char *mandel_last_error(void);

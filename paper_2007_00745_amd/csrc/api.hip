@@ -276,7 +276,7 @@ int mandel_render_sched(const mandel_window *w, int32_t m, int32_t n, int32_t ma
     a.out = out;
     a.order = s.order;
     a.tile_cost = rows ? nullptr : s.tile_cost;
-    a.claims = rows ? nullptr : s.claims;
+    a.claims = s.claims;
     a.stats = s.stats;
 
     unsigned long long *head = nullptr;
@@ -294,7 +294,7 @@ int mandel_render_sched(const mandel_window *w, int32_t m, int32_t n, int32_t ma
         if (rc)
             return rc;
     }
-    hipError_t e = launch_clear(head, a.tile_cost, a.claims, a.tile_cost || a.claims ? ntiles : 0, st);
+    hipError_t e = launch_clear(head, a.tile_cost, a.claims, a.tile_cost || a.claims ? ntiles : 0, a.stats, st);
     if (e != hipSuccess)
         return hip_fail(e, "clear launch");
     e = launch_render(a, s.policy, false, s.check_every == 0, grid, block, st);

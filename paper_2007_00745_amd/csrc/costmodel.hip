@@ -288,6 +288,50 @@ __global__ void __launch_bounds__(256) train_loss_kernel(int32_t B, const float 
         *loss = red[0] / (float)B;
 }
 
+// ---- standardisation and targets ---------------------------------------------------
+// One block per feature column: mean and (population) standard deviation.
+__global__ void __launch_bounds__(256) norm_kernel(float *params, const float *feat, int64_t n)
+{
+    __shared__ double red[2][256];
+    const int c = blockIdx.x;
+    double s = 0.0, s2 = 0.0;
+    for (int64_t r = threadIdx.x; r < n; r += blockDim.x) {
+        const double v = (double)feat[r * NF + c];
+        s += v;
+        s2 += v * v;
+    }
+    red[0][threadIdx.x] = s;
+    red[1][threadIdx.x] = s2;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            red[0][threadIdx.x] += red[0][threadIdx.x + w];
+            red[1][threadIdx.x] += red[1][threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double mu = red[0][0] / (double)n;
+        double var = red[1][0] / (double)n - mu * mu;
+        if (var < 0.0)
+            var = 0.0;
+        double sd = sqrt(var);
+        if (sd < 1e-6)
+            sd = 1e-6;
+        params[OFF_MU + c] = (float)mu;
+        params[OFF_ISD + c] = (float)(1.0 / sd);
+    }
+}
+
+__global__ void targets_kernel(const int64_t *cost, int64_t n, float *target)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) {
+        const int64_t c = cost[t] > 1 ? cost[t] : 1;
+        target[t] = (float)log((double)c);
+    }
+}
+
 // ---- descending bucket order ---------------------------------------------------
 constexpr int NB = MANDEL_ORDER_BUCKETS;
 
@@ -465,6 +509,32 @@ int mandel_mlp_train_step(float *params, float *adam_m, float *adam_v, int32_t t
     hipError_t e = launch_mlp_train_step(params, adam_m, adam_v, t, x, target, idx, batch, lr,
                                          loss, work, (hipStream_t)stream);
     return e == hipSuccess ? MANDEL_OK : hip_fail(e, "mlp train launch");
+}
+
+int mandel_mlp_set_norm(float *params, const float *feat, int64_t n, void *stream)
+{
+    clear_error();
+    if (!params || !feat || n < 1)
+        return fail(MANDEL_EINVAL, "need params, feat and n >= 1");
+    hipLaunchKernelGGL(norm_kernel, dim3(NF), dim3(256), 0, (hipStream_t)stream, params, feat,
+                       n);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? MANDEL_OK : hip_fail(e, "norm launch");
+}
+
+int mandel_cost_targets(const int64_t *cost, int64_t n, float *target, void *stream)
+{
+    clear_error();
+    if (n < 0)
+        return fail(MANDEL_EINVAL, "negative n");
+    if (n == 0)
+        return MANDEL_OK;
+    if (!cost || !target)
+        return fail(MANDEL_EINVAL, "null pointer");
+    hipLaunchKernelGGL(targets_kernel, dim3(blocks_for(n, 256)), dim3(256), 0,
+                       (hipStream_t)stream, cost, n, target);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? MANDEL_OK : hip_fail(e, "targets launch");
 }
 
 int mandel_order_desc(const float *keys, int64_t n, int32_t *perm, void *stream)

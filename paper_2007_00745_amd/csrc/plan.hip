@@ -162,7 +162,7 @@ int enqueue(mandel_plan *p, int32_t *out, const mandel_launch &la, hipStream_t s
     int rc = tile_grid(sc, true, p->ntiles, &grid, &block);
     if (rc)
         return rc;
-    e = launch_clear(p->d_head, la.tile_cost, nullptr, la.tile_cost ? p->ntiles : 0, s);
+    e = launch_clear(p->d_head, la.tile_cost, nullptr, la.tile_cost ? p->ntiles : 0, la.stats, s);
     if (e != hipSuccess)
         return hip_fail(e, "clear launch");
     e = launch_render(a, policy, true, true, grid, block, s);

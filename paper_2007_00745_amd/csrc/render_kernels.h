@@ -41,13 +41,13 @@ struct RenderArgs {
     const int32_t *order;          // ORDERED: queue slot -> tile id
     int64_t *tile_cost;            // optional: sum of counts per tile
     int32_t *claims;               // optional: claims per tile
-    uint64_t *stats;               // optional: [wave iterations, sum counts, waves, items]
+    uint64_t *stats;               // optional: uint64[8], see mandel_sched.stats
 };
 
 hipError_t launch_render(const RenderArgs &a, int policy, bool batch, bool defer, dim3 grid,
                          dim3 block, hipStream_t s);
 hipError_t launch_clear(unsigned long long *head, int64_t *tile_cost, int32_t *claims,
-                        int64_t ntiles, hipStream_t s);
+                        int64_t ntiles, uint64_t *stats, hipStream_t s);
 int persistent_blocks_per_cu(int policy, bool batch, bool defer, int threads);
 
 } // namespace mandel

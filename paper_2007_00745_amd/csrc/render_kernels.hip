@@ -106,12 +106,18 @@ __device__ __forceinline__ int32_t find_view(const ViewDesc *views, int32_t nvie
 
 // Clears the queue head and the optional per-tile logs before a launch.
 __global__ void clear_kernel(unsigned long long *head, int64_t *tile_cost, int32_t *claims,
-                             int64_t ntiles)
+                             int64_t ntiles, uint64_t *stats)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
     if (i == 0 && head)
         *head = 0ull;
+    if (i == 0 && stats) {
+        // per-launch timestamps (wall clock ticks): first claim, queue dry, last exit
+        stats[4] = ~0ull;
+        stats[5] = ~0ull;
+        stats[6] = 0ull;
+    }
     for (int64_t t = i; t < ntiles; t += stride) {
         if (tile_cost)
             tile_cost[t] = 0;
@@ -163,6 +169,14 @@ __global__ void __launch_bounds__(1024) render_kernel(RenderArgs a)
                         if (lane == 0)
                             q = atomicAdd(a.head, (unsigned long long)a.grain);
                         int64_t qb = bcast_i64((int64_t)q);
+                        if (a.stats && lane == 0) {
+                            if (qb == 0)
+                                atomicMin((unsigned long long *)&a.stats[4],
+                                          (unsigned long long)wall_clock64());
+                            if (qb >= a.ntiles && qb < a.ntiles + a.grain)
+                                atomicMin((unsigned long long *)&a.stats[5],
+                                          (unsigned long long)wall_clock64());
+                        }
                         if (qb >= a.ntiles)
                             return false;
                         q_next = qb;
@@ -238,6 +252,8 @@ __global__ void __launch_bounds__(1024) render_kernel(RenderArgs a)
                     return false;
                 row = k < q ? r + k * W : q * W + (k - q);
             }
+            if (a.claims && lane == 0)
+                atomicAdd(&a.claims[row], r + 1); // ownership log: worker r + 1 per take
             s_view = 0;
             s_x0 = 0;
             s_y0 = row;
@@ -478,6 +494,7 @@ __global__ void __launch_bounds__(1024) render_kernel(RenderArgs a)
             atomicAdd((unsigned long long *)&a.stats[1], (unsigned long long)tot);
             atomicAdd((unsigned long long *)&a.stats[2], 1ull);
             atomicAdd((unsigned long long *)&a.stats[3], (unsigned long long)taken);
+            atomicMax((unsigned long long *)&a.stats[6], (unsigned long long)wall_clock64());
         }
     }
 }
@@ -531,7 +548,7 @@ hipError_t launch_render(const RenderArgs &a, int policy, bool batch, bool defer
 }
 
 hipError_t launch_clear(unsigned long long *head, int64_t *tile_cost, int32_t *claims,
-                        int64_t ntiles, hipStream_t s)
+                        int64_t ntiles, uint64_t *stats, hipStream_t s)
 {
     int64_t blocks = (ntiles + 255) / 256;
     if (blocks < 1)
@@ -539,7 +556,7 @@ hipError_t launch_clear(unsigned long long *head, int64_t *tile_cost, int32_t *c
     if (blocks > 4096)
         blocks = 4096;
     hipLaunchKernelGGL(clear_kernel, dim3((unsigned)blocks), dim3(256), 0, s, head, tile_cost,
-                       claims, ntiles);
+                       claims, ntiles, stats);
     return hipGetLastError();
 }
 

@@ -127,6 +127,13 @@ def lib() -> ctypes.CDLL:
         L.mandel_mlp_train_step.restype = ctypes.c_int
         L.mandel_order_desc.argtypes = [P, i64, P, P]
         L.mandel_order_desc.restype = ctypes.c_int
+        L.mandel_mlp_set_norm.argtypes = [P, P, i64, P]
+        L.mandel_mlp_set_norm.restype = ctypes.c_int
+        L.mandel_cost_targets.argtypes = [P, i64, P, P]
+        L.mandel_cost_targets.restype = ctypes.c_int
+        L.mandel_plan_autotune.argtypes = [ctypes.POINTER(ViewC), i32, i32,
+                                           ctypes.POINTER(Tuning), ctypes.POINTER(i32), P]
+        L.mandel_plan_autotune.restype = ctypes.c_int
         _lib = L
         return L
 
@@ -197,21 +204,38 @@ def render_sched(window, m: int, n: int, max_iter: int, R: float, out=None, stre
 
 # ---- batches ----------------------------------------------------------------
 
+def _view_array(views, offs):
+    arr = (ViewC * len(views))()
+    for k, v in enumerate(views):
+        arr[k] = ViewC(Window(*[float(t) for t in v.window]), int(v.m), int(v.n),
+                       int(v.max_iter), 0, float(v.R), int(offs[k]))
+    return arr
+
+
+def _packed_offsets(views):
+    offs, acc = [], 0
+    for v in views:
+        offs.append(acc)
+        acc += v.m * v.n
+    return offs
+
+
+def autotune(views, max_sample: int = 8, stream=None) -> tuple[dict, int]:
+    """mandel_plan_autotune: (chosen tuning, number of timed trial launches)."""
+    arr = _view_array(views, _packed_offsets(views))
+    best, trials = Tuning(), ctypes.c_int32()
+    check(lib().mandel_plan_autotune(arr, len(views), int(max_sample), ctypes.byref(best),
+                                     ctypes.byref(trials), _stream(stream)))
+    return best.as_dict(), int(trials.value)
+
+
 class Plan:
     """A batch plan (mandel_plan_*): views rendered by one persistent launch."""
 
     def __init__(self, views, tuning: dict | None = None, out_offsets=None):
         n = len(views)
-        arr = (ViewC * n)()
-        offs = out_offsets
-        if offs is None:
-            offs, acc = [], 0
-            for v in views:
-                offs.append(acc)
-                acc += v.m * v.n
-        for k, v in enumerate(views):
-            arr[k] = ViewC(Window(*[float(t) for t in v.window]), int(v.m), int(v.n),
-                           int(v.max_iter), 0, float(v.R), int(offs[k]))
+        offs = _packed_offsets(views) if out_offsets is None else list(out_offsets)
+        arr = _view_array(views, offs)
         tu = Tuning(**(tuning or {}))
         h = ctypes.c_void_p()
         check(lib().mandel_plan_create(arr, n, ctypes.byref(tu), ctypes.byref(h)))
@@ -289,3 +313,16 @@ def order_desc(keys, perm=None, stream=None):
         perm = torch.empty(n, dtype=torch.int32, device=keys.device)
     check(lib().mandel_order_desc(_ptr(keys), n, _ptr(perm), _stream(stream)))
     return perm
+
+
+def mlp_set_norm(params, feat, stream=None):
+    check(lib().mandel_mlp_set_norm(_ptr(params), _ptr(feat), feat.shape[0], _stream(stream)))
+    return params
+
+
+def cost_targets(cost, target=None, stream=None):
+    import torch
+    if target is None:
+        target = torch.empty(cost.numel(), dtype=torch.float32, device=cost.device)
+    check(lib().mandel_cost_targets(_ptr(cost), cost.numel(), _ptr(target), _stream(stream)))
+    return target

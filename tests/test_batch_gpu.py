@@ -105,7 +105,7 @@ def test_plan_tile_cost_and_stats(small_batch):
     views, want = small_batch
     plan = native.Plan(views, dict(tile_w=32, tile_h=8))
     cost = torch.full((plan.ntiles,), -5, dtype=torch.int64, device="cuda")
-    stats = torch.zeros(4, dtype=torch.int64, device="cuda")
+    stats = torch.zeros(8, dtype=torch.int64, device="cuda")
     out = torch.empty((plan.out_size(),), dtype=torch.int32, device="cuda")
     for use_graph in (False, True, True):
         cost.fill_(-5)

@@ -89,7 +89,7 @@ def test_claims_and_costs(c1_ref):
         nt = native.tile_count(v.m, v.n, tw, th)
         claims = torch.full((nt,), 7, dtype=torch.int32, device="cuda")
         cost = torch.full((nt,), -1, dtype=torch.int64, device="cuda")
-        stats = torch.zeros(4, dtype=torch.int64, device="cuda")
+        stats = torch.zeros(8, dtype=torch.int64, device="cuda")
         got = gpu_render(v, tile_w=tw, tile_h=th, grain=g, claims=claims, tile_cost=cost,
                          stats=stats)
         assert np.array_equal(got, c1_ref)
@@ -168,17 +168,23 @@ def test_zoomed_views_small():
         assert np.array_equal(gpu_render(v, check_every=1, tile_w=32, tile_h=2), want)
 
 
-def test_row_partitions_cover_rows():
-    # the kernel's row ownership equals the paper's partitions: worker r of W renders
-    # exactly partition.naive_rows / alternating_rows (checked through the output:
-    # each row is written once and matches the oracle)
-    v = workloads.View(workloads.window_from_bounds(-2, 1, -1.2, 1.2, 101, 40), 101, 40, 300)
+@pytest.mark.parametrize("m", [101, 480])
+def test_row_partitions_ownership(m):
+    # Worker r of W renders exactly the rows the paper assigns it: Sec. III-A (naive
+    # contiguous rows, leftover rows to the last worker) and Sec. III-C (alternating
+    # rows, leftover rows to worker 0).  The kernel logs r + 1 for every row it takes.
+    v = workloads.View(workloads.window_from_bounds(-2, 1, -1.2, 1.2, m, 40), m, 40, 300)
     want = ref(v)
-    for W in (1, 2, 7, 100, 101, 150):
-        for pol, fn in (("static", partition.naive_rows), ("alternating", partition.alternating_rows)):
-            rows = sorted(r for k in range(W) for r in fn(v.m, W, k))
-            assert rows == list(range(v.m))
-            assert np.array_equal(gpu_render(v, policy=pol, workers=W), want)
+    for W in (1, 2, 7, 100, 101, 150, 1000):
+        for pol, fn in (("static", partition.naive_rows),
+                        ("alternating", partition.alternating_rows)):
+            owner = np.zeros(m, dtype=np.int64)
+            for k in range(W):
+                owner[fn(m, W, k)] = k + 1
+            assert np.all(owner > 0)
+            log = torch.full((m,), 99, dtype=torch.int32, device="cuda")
+            assert np.array_equal(gpu_render(v, policy=pol, workers=W, claims=log), want)
+            assert np.array_equal(log.cpu().numpy(), owner), (pol, W)
 
 
 def test_nondefault_stream(c1_ref):

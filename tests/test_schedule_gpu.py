@@ -1,0 +1,123 @@
+"""GPU tests of the schedule layer: the autotuner, the learned longest-first
+order against FCFS (what the trained cost model gains, measured), and the
+stress batch (a 16384 x 16384 deep zoom of width 1e-12 plus 4096 views of
+512 x 512).  Every schedule must give the same counts as the CPU oracle."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2007_00745_amd import costmodel, native, workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def _log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def _timed(fn, reps=3):
+    fn()
+    torch.cuda.synchronize()
+    best = float("inf")
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn()
+        b.record()
+        torch.cuda.synchronize()
+        best = min(best, a.elapsed_time(b))
+    return best
+
+
+def _sample_check(plan, out, rng, per_view=256, max_views=None):
+    views = plan.views
+    ks = range(len(views)) if max_views is None else rng.choice(len(views), max_views,
+                                                                 replace=False)
+    for k in ks:
+        v, o = views[k], plan.out_offsets[k]
+        if v.pixels == 0:
+            continue
+        idx = rng.integers(0, v.pixels, min(per_view, v.pixels))
+        got = out[o + torch.tensor(idx, device="cuda")].cpu().numpy()
+        want = oracle.render_pixels(v.window, v.m, v.n, v.max_iter, v.R, idx, threads=16)
+        assert np.array_equal(got, want), f"view {k}"
+
+
+def test_autotune_and_tuned_plan():
+    views = workloads.c3_scaled(745, 64, scale=8)
+    tun, trials = native.autotune(views, max_sample=6)
+    _log(f"autotune {tun} after {trials} trials")
+    assert trials > 0
+    assert tun["tile_w"] >= 1 and tun["tile_h"] >= 1 and tun["grain"] >= 1
+    tun2, trials2 = native.autotune(views, max_sample=6)
+    assert tun2 == tun and trials2 == 0  # cached
+    plan = native.Plan(views, tun)
+    out = torch.empty(plan.out_size(), dtype=torch.int32, device="cuda")
+    plan.launch(out)
+    torch.cuda.synchronize()
+    want = [oracle.render(v.window, v.m, v.n, v.max_iter, v.R) for v in views[:12]]
+    for k, w in enumerate(want):
+        o = plan.out_offsets[k]
+        assert np.array_equal(out[o:o + views[k].pixels].cpu().numpy().reshape(w.shape), w)
+    plan.close()
+
+
+def test_learned_order_vs_fcfs():
+    # Train the cost model on views drawn from seeds disjoint from the evaluation batch,
+    # then compare queue orders on the held-out batch: FCFS (submission order), the
+    # probe-sum heuristic, the learned model and the true-cost order (from a logged run).
+    train_views = workloads.training_views(range(1000, 1004), per_seed=16, lo=64, hi=1024)
+    feat, target, _, tplan = costmodel.collect(train_views)
+    params, losses = costmodel.train(feat, target, epochs=8, batch=512, lr=1e-3, seed=0)
+    _log(f"train {tplan.ntiles} tiles, epoch losses {[round(x, 3) for x in losses]}")
+    assert losses[-1] < losses[0]
+
+    views = workloads.c3_scaled(745, 64, scale=4)
+    plan = native.Plan(views)
+    out = torch.empty(plan.out_size(), dtype=torch.int32, device="cuda")
+    cost = torch.empty(plan.ntiles, dtype=torch.int64, device="cuda")
+    plan.launch(out, tile_cost=cost)
+    torch.cuda.synchronize()
+    ref = out.clone()
+    ev = costmodel.evaluate(params, plan.features(), native.cost_targets(cost))
+    _log(f"held-out: {ev}")
+    assert ev["spearman"] > 0.6
+
+    true_perm = torch.argsort(cost, descending=True).to(torch.int32)
+    ms = {}
+    for mode, kw in (("fcfs", {}), ("probe", {}), ("learned", dict(mlp=params)),
+                     ("ordered", dict(order=true_perm))):
+        out.fill_(-1)
+        ms[mode] = _timed(lambda: plan.launch(out, mode=mode, use_graph=True, **kw))
+        assert torch.equal(out, ref), mode
+    _log(f"makespan ms: {ms}; learned gain over FCFS {100 * (1 - ms['learned'] / ms['fcfs']):.1f}%")
+    assert ms["learned"] < 1.5 * ms["fcfs"]
+    _sample_check(plan, out, np.random.default_rng(3), per_view=64)
+    plan.close()
+    tplan.close()
+
+
+def test_stress_batch_c5():
+    views = workloads.c5()
+    plan = native.Plan(views)
+    _log(f"c5: {plan.ntiles} tiles, {plan.npixels} px")
+    out = torch.full((plan.out_size(),), -1, dtype=torch.int32, device="cuda")
+    stats = torch.zeros(8, dtype=torch.int64, device="cuda")
+    plan.launch(out, stats=stats)
+    torch.cuda.synchronize()
+    st = stats.cpu().numpy()
+    _log(f"c5 stats {st.tolist()}")
+    assert int(out.min().item()) >= 1
+    assert st[3] == plan.ntiles
+    rng = np.random.default_rng(747)
+    deep = views[0]
+    idx = rng.integers(0, deep.pixels, 2048)
+    got = out[torch.tensor(idx, device="cuda")].cpu().numpy()
+    want = oracle.render_pixels(deep.window, deep.m, deep.n, deep.max_iter, deep.R, idx,
+                                threads=16)
+    assert np.array_equal(got, want)
+    _sample_check(plan, out, rng, per_view=512, max_views=16)
+    plan.close()
