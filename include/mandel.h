@@ -293,6 +293,10 @@ int mandel_cost_targets(const int64_t *cost, int64_t n, float *target, void *str
 int mandel_plan_autotune(const mandel_view *views, int32_t nviews, int32_t max_sample,
                          mandel_tuning *best, int32_t *trials, void *stream);
 
+/* Properties of the current device used by the library: compute units and
+ * the rate of the wall clock that stamps mandel_sched.stats[4..6] (kHz). */
+int mandel_device_info(int32_t *compute_units, int32_t *wall_clock_khz);
+
 /* Text of the last error on this thread ("" if none). */
 const char *mandel_last_error(void);
 

@@ -235,6 +235,29 @@ const char *mandel_last_error(void) { return g_err.c_str(); }
 
 const char *mandel_version(void) { return "mandel-gfx950 0.1"; }
 
+int mandel_device_info(int32_t *compute_units, int32_t *wall_clock_khz)
+{
+    clear_error();
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return hip_fail(e, "hipGetDevice");
+    int v = 0;
+    if (compute_units) {
+        e = hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e != hipSuccess)
+            return hip_fail(e, "hipDeviceGetAttribute");
+        *compute_units = v;
+    }
+    if (wall_clock_khz) {
+        e = hipDeviceGetAttribute(&v, hipDeviceAttributeWallClockRate, dev);
+        if (e != hipSuccess)
+            return hip_fail(e, "hipDeviceGetAttribute");
+        *wall_clock_khz = v;
+    }
+    return MANDEL_OK;
+}
+
 int64_t mandel_tile_count(int32_t m, int32_t n, int32_t tile_w, int32_t tile_h)
 {
     return tile_count(m, n, tile_w, tile_h);

@@ -134,6 +134,8 @@ def lib() -> ctypes.CDLL:
         L.mandel_plan_autotune.argtypes = [ctypes.POINTER(ViewC), i32, i32,
                                            ctypes.POINTER(Tuning), ctypes.POINTER(i32), P]
         L.mandel_plan_autotune.restype = ctypes.c_int
+        L.mandel_device_info.argtypes = [ctypes.POINTER(i32), ctypes.POINTER(i32)]
+        L.mandel_device_info.restype = ctypes.c_int
         _lib = L
         return L
 
@@ -326,3 +328,9 @@ def cost_targets(cost, target=None, stream=None):
         target = torch.empty(cost.numel(), dtype=torch.float32, device=cost.device)
     check(lib().mandel_cost_targets(_ptr(cost), cost.numel(), _ptr(target), _stream(stream)))
     return target
+
+
+def device_info() -> dict:
+    cus, khz = ctypes.c_int32(), ctypes.c_int32()
+    check(lib().mandel_device_info(ctypes.byref(cus), ctypes.byref(khz)))
+    return {"compute_units": int(cus.value), "wall_clock_khz": int(khz.value)}
