@@ -1,18 +1,21 @@
 """Benchmark: escape-time Mandelbrot on one MI355X.
 
 Headline workload (the 8192 x 8192 full view): re in [-2, 1], im in
-[-1.2, 1.2], pixel centres, R = 2, max_iter 10000, FP64, int32 counts.  One
-step = one mandel_render of the whole view (persistent FCFS queue of 64 x 8
-tiles) with the output resident in HBM.  value = pixel-iterations per second
-(sum of the counts / mean step time).  FP64 FLOP/s counts 7 operations per
-iteration (x*x, y*y, x*y, 2*, -, +cx, +cy).
+[-1.2, 1.2], pixel centres, R = 2, max_iter 10000, FP64, int32 counts.
+One step = one pass of the whole hot path over the view, with the output
+resident in HBM: one replay of the plan's hipGraph = probe features (64 probe
+pixels per 64 x 8 tile) -> cost-model MLP -> descending tile order ->
+persistent render over the ordered device queue.  The cost model is trained
+once before timing (on views disjoint from every timed workload).
+value = pixel-iterations per second (sum of the counts / mean step time);
+FP64 FLOP/s counts 7 operations per iteration (x*x, y*y, x*y, 2*, -, +cx, +cy).
 
-Also reported (not the value):
-  * makespans on the uneven 64-view batch (seed 745): per-view static rows
-    (paper Sec. III-A) and alternating rows (Sec. III-C) at their best worker
-    count, per-view FCFS, and one batched persistent launch (hipGraph) in FCFS,
-    probe-heuristic, learned-model and true-cost orders;
-  * the oracle's rate on the host cores for a bounded sample.
+Also reported (not the value): the plain mandel_render (FCFS queue in tile
+order) and the order by true tile costs on the same view; makespans on the
+uneven 64-view batch (seed 745) for per-view static rows (paper Sec. III-A),
+alternating rows (Sec. III-C), per-view FCFS and one batched launch in FCFS,
+probe-heuristic, learned and true-cost orders; the oracle's rate on the host
+cores for a bounded sample.
 
 Prints one JSON line.  --gpus N > 1 is refused: this build runs on one GPU.
 """
@@ -103,7 +106,26 @@ def tail_fraction(st, clock_khz):
             "tail_fraction": (st[6] - st[5]) / (st[6] - st[4])}
 
 
-def makespans(torch, native, workloads, costmodel, reps: int, clock_khz: float) -> dict:
+def train_cost_model(torch, native, workloads, costmodel):
+    """Cost model for the ordered launches: tile costs logged from views of the
+    uneven-batch distribution (seeds 1000-1015) and four full views of other
+    sizes and limits, 200k tiles sampled, 30 epochs of Adam (all in the kernels)."""
+    t0 = time.perf_counter()
+    tv = workloads.training_views(range(1000, 1016), per_seed=4)
+    tv += [workloads.c2(side, mi) for side, mi in ((1024, 2000), (2048, 5000), (1536, 20000),
+                                                   (768, 800))]
+    feat, target, _, tplan = costmodel.collect(tv)
+    params, losses = costmodel.train(feat, target, epochs=30, batch=512, lr=1e-3, seed=0)
+    torch.cuda.synchronize()
+    info = {"train_tiles_logged": int(tplan.ntiles),
+            "train_samples": min(int(tplan.ntiles), 200000), "epochs": 30, "batch": 512,
+            "final_train_loss": losses[-1], "seconds": time.perf_counter() - t0}
+    tplan.close()
+    return params, info
+
+
+def makespans(torch, native, workloads, costmodel, reps: int, clock_khz: float,
+              params) -> dict:
     """Uneven 64-view batch: per-view row partitions and FCFS vs one batched launch."""
     res = {}
     views = workloads.c3()
@@ -142,17 +164,8 @@ def makespans(torch, native, workloads, costmodel, reps: int, clock_khz: float) 
     assert torch.equal(out, ref), "row partitions changed the counts"
     ms["fcfs_per_view"] = {"ms": timed_ms(torch, lambda: per_view("fcfs", None), 1, "fcfs/view")}
 
-    log("makespan: training the cost model")
-    t0 = time.perf_counter()
-    tv = workloads.training_views(range(1000, 1016), per_seed=4)
-    feat, target, _, tplan = costmodel.collect(tv, tun)
-    params, losses = costmodel.train(feat, target, epochs=30, batch=512, lr=1e-3, seed=0)
-    torch.cuda.synchronize()
-    res["cost_model"] = {"train_tiles_logged": int(tplan.ntiles),
-                         "train_samples": min(int(tplan.ntiles), 200000), "epochs": 30,
-                         "final_train_loss": losses[-1], "seconds": time.perf_counter() - t0}
-    res["cost_model"].update(costmodel.evaluate(params, plan.features(), native.cost_targets(cost)))
-    tplan.close()
+    res["cost_model_eval"] = costmodel.evaluate(params, plan.features(),
+                                                native.cost_targets(cost))
     true_perm = torch.argsort(cost, descending=True).to(torch.int32)
     names = {"fcfs": "fcfs", "probe": "probe_lpt", "learned": "learned_lpt",
              "ordered": "true_cost_lpt"}
@@ -176,6 +189,25 @@ def makespans(torch, native, workloads, costmodel, reps: int, clock_khz: float) 
     return res
 
 
+def comparisons(torch, native, view, plan, out, cost, sum_counts, stream) -> dict:
+    """The plain mandel_render (FCFS in tile order) and the true-cost order on the
+    headline view, and the cost of the probe features alone."""
+    comp = {}
+    plain = torch.empty((view.m, view.n), dtype=torch.int32, device="cuda")
+    comp["plain_fcfs_render_ms"] = timed_ms(
+        torch, lambda: native.render(view.window, view.m, view.n, view.max_iter, view.R,
+                                     out=plain, stream=stream), 3, "plain FCFS")
+    assert torch.equal(plain.view(-1), out), "plain FCFS and the ordered plan disagree"
+    true_perm = torch.argsort(cost, descending=True).to(torch.int32)
+    comp["true_cost_order_ms"] = timed_ms(
+        torch, lambda: plan.launch(out, mode="ordered", order=true_perm, use_graph=True,
+                                   stream=stream), 3, "true-cost order")
+    comp["features_ms"] = timed_ms(torch, lambda: plan.features(stream=stream), 3, "features")
+    for k in ("plain_fcfs_render_ms", "true_cost_order_ms"):
+        comp[k.replace("_ms", "_pixel_iterations_per_s")] = sum_counts / (comp[k] / 1e3)
+    return comp
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -189,6 +221,10 @@ def main():
     ap.add_argument("--cpu-rows-step", type=int, default=4)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 1 GiB device-to-device copy (counter calibration)")
+    ap.add_argument("--profile", action="store_true",
+                    help="short run for counter collection: no training (the step orders "
+                         "tiles by the probe heuristic), no comparisons, no makespans, "
+                         "no CPU baseline")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -204,23 +240,34 @@ def main():
     torch.cuda.set_device(0)
     dinfo = native.device_info()
     clock_khz = float(dinfo["wall_clock_khz"]) or 100000.0
-    out = torch.empty((view.m, view.n), dtype=torch.int32, device="cuda")
     stream = torch.cuda.current_stream()
+    if args.profile:
+        args.no_makespan = args.no_cpu_baseline = True
+        params, cm_info, mode = None, {}, "probe"
+    else:
+        log("bench: training the cost model")
+        params, cm_info = train_cost_model(torch, native, workloads, costmodel)
+        mode = "learned"
+    plan = native.Plan([view])
+    out = torch.empty(plan.out_size(), dtype=torch.int32, device="cuda")
 
     def step():
-        native.render(view.window, view.m, view.n, view.max_iter, view.R, out=out, stream=stream)
+        plan.launch(out, mode=mode, mlp=params, use_graph=True, stream=stream)
 
     log(f"bench: {view.m}x{view.n} max_iter {view.max_iter}; warmup {args.warmup}")
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
+    cost = torch.empty(plan.ntiles, dtype=torch.int64, device="cuda")
     stats = torch.zeros(8, dtype=torch.int64, device="cuda")
-    native.render_sched(view.window, view.m, view.n, view.max_iter, view.R, out=out,
-                        stream=stream, stats=stats)
+    plan.launch(out, mode=mode, mlp=params, stats=stats, tile_cost=cost, stream=stream)
     torch.cuda.synchronize()
     sum_counts = int(out.sum(dtype=torch.int64).item())
+    assert sum_counts == int(cost.sum().item())
     st = [int(v) for v in stats.cpu().tolist()]
     lane_occ = st[1] / (64.0 * st[0]) if st[0] else None
+    if params is not None:
+        cm_info.update(costmodel.evaluate(params, plan.features(), native.cost_targets(cost)))
 
     log(f"bench: timing {args.steps} steps")
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
@@ -239,6 +286,28 @@ def main():
     value = sum_counts / sec
     tflops = FLOPS_PER_ITER * sum_counts / sec / 1e12
     log(f"bench: {ms_mean:.3f} ms/step, {tflops:.2f} TFLOP/s")
+
+    # The dominant kernel alone: the same learned order computed once through the
+    # public calls, then only the ordered render (clear + render kernels) between events.
+    if params is not None:
+        keys = native.mlp_forward(params, plan.features(stream=stream), stream=stream)
+    else:
+        keys = native.cost_targets(cost, stream=stream)  # profile runs: true-cost order
+    lperm = native.order_desc(keys, stream=stream)
+    rev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(args.steps)]
+    for a, b in rev:
+        a.record(stream)
+        plan.launch(out, mode="ordered", order=lperm, stream=stream)
+        b.record(stream)
+    torch.cuda.synchronize()
+    render_ms = sum(a.elapsed_time(b) for a, b in rev) / len(rev)
+    render_tflops = FLOPS_PER_ITER * sum_counts / (render_ms / 1e3) / 1e12
+    log(f"bench: ordered render alone {render_ms:.3f} ms, {render_tflops:.2f} TFLOP/s")
+    comp = None
+    if not args.profile:
+        comp = comparisons(torch, native, view, plan, out, cost, sum_counts, stream)
+        comp["render_kernel_ms"] = render_ms
 
     if args.copy_calibration:
         a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
@@ -262,7 +331,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"full view {view.m}x{view.n}, re[-2,1] x im[-1.2,1.2], "
                                f"pixel centres, R=2, max_iter {view.max_iter}",
-                   "policy": "persistent FCFS tile queue, 64x8 tiles",
+                   "policy": "hipGraph: probe features -> cost-model MLP -> descending "
+                             "order -> persistent ordered tile queue, 64x8 tiles",
                    "parallelism": "single GPU"},
         "sum_counts": sum_counts,
         "fp64_tflops": tflops,
@@ -272,14 +342,19 @@ def main():
         "ms_min": min(ms),
         "wall_s": wall,
         "device": dinfo,
-        "roofline": {"bound": "alu", "achieved": tflops, "peak": FP64_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": tflops / FP64_PEAK_TFLOPS,
-                     "traffic": measured_traffic()},
+        "roofline": {"bound": "alu", "achieved": render_tflops, "peak": FP64_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": render_tflops / FP64_PEAK_TFLOPS,
+                     "traffic": measured_traffic(),
+                     "kernel": "render_kernel (ordered queue, batch, deferred tests)",
+                     "flops_per_launch": FLOPS_PER_ITER * sum_counts,
+                     "launch_ms": render_ms},
         "kernel_source_sha256_16": kernel_sha(),
+        "cost_model": cm_info,
+        "comparisons": comp,
     }
     if not args.no_makespan:
         res["makespan"] = makespans(torch, native, workloads, costmodel, args.makespan_reps,
-                                    clock_khz)
+                                    clock_khz, params)
     if not args.no_cpu_baseline:
         threads = min(16, os.cpu_count() or 1)
         log(f"bench: cpu baseline on {threads} threads")

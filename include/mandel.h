@@ -191,6 +191,10 @@ typedef struct mandel_launch {
     const float *mlp;        /* device float[MANDEL_MLP_PARAMS], LEARNED_LPT: the cost model */
     int64_t *tile_cost;      /* device int64[ntiles] or NULL: sum of counts per tile */
     uint64_t *stats;         /* device uint64[8] or NULL (as in mandel_sched) */
+    int32_t probe_cap;       /* PROBE_LPT / LEARNED_LPT: probe iteration cap of the
+                                features (see mandel_plan_features) [128]; a model
+                                must be used with the cap it was trained with */
+    int32_t reserved;
 } mandel_launch;
 
 /*

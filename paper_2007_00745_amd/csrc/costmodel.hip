@@ -72,18 +72,20 @@ __global__ void __launch_bounds__(256) features_kernel(const ViewDesc *views, in
     const double cx = vd.cx0 + px;
     const double cy = vd.cy0 + py;
     const int32_t cap = vd.max_iter < probe_cap ? vd.max_iter : probe_cap;
+    // min(count, cap): test z_{k-1} before forming z_k, reusing its squares; the
+    // test of z_cap is not needed because the count is capped at cap anyway.
     double x = 0.0, y = 0.0;
     int32_t cnt = cap;
-    for (int32_t it = 1; it <= cap; ++it) {
+    for (int32_t k = 1; k <= cap; ++k) {
         const double xx = x * x;
         const double yy = y * y;
+        if (xx + yy > vd.R2) {
+            cnt = k - 1;
+            break;
+        }
         const double tt = x * y;
         x = (xx - yy) + cx;
         y = __builtin_fma(2.0, tt, cy);
-        if (x * x + y * y > vd.R2) {
-            cnt = it;
-            break;
-        }
     }
     float *f = feat + t * NF;
     f[4 + lane] = logf(1.0f + (float)cnt) / logf(1.0f + (float)cap);
@@ -102,13 +104,13 @@ __global__ void __launch_bounds__(256) features_kernel(const ViewDesc *views, in
 }
 
 // ---- probe-sum heuristic key: ln(1 + sum of the (capped) probe counts) ------
-__global__ void probe_key_kernel(const float *feat, int64_t n, float *keys)
+__global__ void probe_key_kernel(const float *feat, int64_t n, float probe_cap, float *keys)
 {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n)
         return;
     const float *f = feat + t * NF;
-    const float cap = fminf(expf(f[3]), 128.0f);
+    const float cap = fminf(rintf(expf(f[3])), probe_cap);
     const float L = logf(1.0f + cap);
     float s = 0.0f;
     for (int k = 0; k < 64; ++k)
@@ -117,6 +119,8 @@ __global__ void probe_key_kernel(const float *feat, int64_t n, float *keys)
 }
 
 // ---- MLP inference: one row per thread, parameters staged in LDS -----------
+// The cost model is FP32 and checked within tolerances, so its dot products use
+// fused multiply-add (fmaf) although the file is compiled without contraction.
 __global__ void __launch_bounds__(256) mlp_forward_kernel(const float *params, const float *x,
                                                           int64_t n, float *y)
 {
@@ -136,7 +140,7 @@ __global__ void __launch_bounds__(256) mlp_forward_kernel(const float *params, c
         const float xi = (xr[i] - P[OFF_MU + i]) * P[OFF_ISD + i];
 #pragma unroll
         for (int o = 0; o < NH; ++o)
-            h[o] += P[OFF_W1 + o * NF + i] * xi;
+            h[o] = fmaf(P[OFF_W1 + o * NF + i], xi, h[o]);
     }
 #pragma unroll
     for (int o = 0; o < NH; ++o)
@@ -146,8 +150,8 @@ __global__ void __launch_bounds__(256) mlp_forward_kernel(const float *params, c
         float a = P[OFF_B2 + o];
 #pragma unroll
         for (int i = 0; i < NH; ++i)
-            a += P[OFF_W2 + o * NH + i] * h[i];
-        out += P[OFF_W3 + o] * fmaxf(a, 0.0f);
+            a = fmaf(P[OFF_W2 + o * NH + i], h[i], a);
+        out = fmaf(P[OFF_W3 + o], fmaxf(a, 0.0f), out);
     }
     y[row] = out;
 }
@@ -174,7 +178,7 @@ __global__ void __launch_bounds__(256) train_forward_kernel(const float *params,
         const float xi = (xr[i] - params[OFF_MU + i]) * params[OFF_ISD + i];
 #pragma unroll
         for (int o = 0; o < NH; ++o)
-            h[o] += params[OFF_W1 + o * NF + i] * xi;
+            h[o] = fmaf(params[OFF_W1 + o * NF + i], xi, h[o]);
     }
 #pragma unroll
     for (int o = 0; o < NH; ++o) {
@@ -186,9 +190,9 @@ __global__ void __launch_bounds__(256) train_forward_kernel(const float *params,
         float a = params[OFF_B2 + o];
 #pragma unroll
         for (int i = 0; i < NH; ++i)
-            a += params[OFF_W2 + o * NH + i] * h[i];
+            a = fmaf(params[OFF_W2 + o * NH + i], h[i], a);
         A2[(size_t)b * NH + o] = a;
-        out += params[OFF_W3 + o] * fmaxf(a, 0.0f);
+        out = fmaf(params[OFF_W3 + o], fmaxf(a, 0.0f), out);
     }
     const float e = out - target[row];
     const float g = 2.0f * e / (float)B;
@@ -352,15 +356,46 @@ __global__ void zero_u32_kernel(uint32_t *p, int n)
         p[q] = 0u;
 }
 
+// Runs f(bucket, lanes, leader) once per distinct bucket among the valid lanes of
+// the wavefront (exec must be full): neighbouring tiles often share a bucket, and
+// one atomic per distinct bucket avoids serialising on a single address.
+template <typename F>
+__device__ __forceinline__ void per_distinct_bucket(bool valid, int b, F &&f)
+{
+    uint64_t pending = __builtin_amdgcn_ballot_w64(valid);
+    while (pending) {
+        const int leader = __builtin_ctzll(pending);
+        const int lb = __shfl(b, leader, 64);
+        const uint64_t same = __builtin_amdgcn_ballot_w64(valid && b == lb) & pending;
+        f(lb, same, leader);
+        pending &= ~same;
+    }
+}
+
+__device__ __forceinline__ uint32_t lanes_below(uint64_t mask)
+{
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
 __global__ void __launch_bounds__(1024) hist_kernel(const float *keys, int64_t n, uint32_t *hist)
 {
     __shared__ uint32_t h[NB];
     for (int q = threadIdx.x; q < NB; q += blockDim.x)
         h[q] = 0u;
     __syncthreads();
-    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n;
-         t += (int64_t)gridDim.x * blockDim.x)
-        atomicAdd(&h[bucket_of(keys[t])], 1u);
+    const int lane = threadIdx.x & 63;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t start = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63);
+    for (int64_t t0 = start; t0 < n; t0 += stride) { // wave-uniform trip count
+        const int64_t t = t0 + lane;
+        const bool valid = t < n;
+        const int b = valid ? bucket_of(keys[t]) : 0;
+        per_distinct_bucket(valid, b, [&](int lb, uint64_t same, int leader) {
+            if (lane == leader)
+                atomicAdd(&h[lb], (uint32_t)__popcll(same));
+        });
+    }
     __syncthreads();
     for (int q = threadIdx.x; q < NB; q += blockDim.x)
         if (h[q])
@@ -397,10 +432,17 @@ __global__ void __launch_bounds__(1024) scan_kernel(const uint32_t *hist, uint32
 __global__ void scatter_kernel(const float *keys, int64_t n, uint32_t *cursor, int32_t *perm)
 {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n)
-        return;
-    const uint32_t pos = atomicAdd(&cursor[bucket_of(keys[t])], 1u);
-    perm[pos] = (int32_t)t;
+    const int lane = threadIdx.x & 63;
+    const bool valid = t < n;
+    const int b = valid ? bucket_of(keys[t]) : 0;
+    per_distinct_bucket(valid, b, [&](int lb, uint64_t same, int leader) {
+        uint32_t base = 0;
+        if (lane == leader)
+            base = atomicAdd(&cursor[lb], (uint32_t)__popcll(same));
+        base = (uint32_t)__shfl((int)base, leader, 64);
+        if ((same >> lane) & 1u)
+            perm[base + lanes_below(same)] = (int32_t)t;
+    });
 }
 
 unsigned blocks_for(int64_t n, int threads, int64_t cap = 1 << 30)
@@ -423,10 +465,11 @@ hipError_t launch_features(const ViewDesc *views, int32_t nviews, int64_t ntiles
     return hipGetLastError();
 }
 
-hipError_t launch_probe_key(const float *feat, int64_t n, float *keys, hipStream_t s)
+hipError_t launch_probe_key(const float *feat, int64_t n, int32_t probe_cap, float *keys,
+                            hipStream_t s)
 {
     hipLaunchKernelGGL(probe_key_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, feat, n,
-                       keys);
+                       (float)probe_cap, keys);
     return hipGetLastError();
 }
 

@@ -24,6 +24,7 @@ struct GraphEntry {
     const float *mlp;
     int64_t *tile_cost;
     uint64_t *stats;
+    int32_t probe_cap;
     hipGraph_t graph;
     hipGraphExec_t exec;
 };
@@ -119,11 +120,11 @@ int enqueue(mandel_plan *p, int32_t *out, const mandel_launch &la, hipStream_t s
         policy = POLICY_ORDERED_TILES;
     } else if (la.mode == MANDEL_PLAN_PROBE_LPT || la.mode == MANDEL_PLAN_LEARNED_LPT) {
         e = launch_features(p->d_views, (int32_t)p->views.size(), p->ntiles, p->tune.tile_w,
-                            p->tune.tile_h, 128, p->d_feat, s);
+                            p->tune.tile_h, la.probe_cap, p->d_feat, s);
         if (e != hipSuccess)
             return hip_fail(e, "features launch");
         if (la.mode == MANDEL_PLAN_PROBE_LPT)
-            e = launch_probe_key(p->d_feat, p->ntiles, p->d_keys, s);
+            e = launch_probe_key(p->d_feat, p->ntiles, la.probe_cap, p->d_keys, s);
         else
             e = launch_mlp_forward(la.mlp, p->d_feat, p->ntiles, p->d_keys, s);
         if (e != hipSuccess)
@@ -263,6 +264,10 @@ int mandel_plan_launch(mandel_plan *p, int32_t *out, const mandel_launch *args, 
         return fail(MANDEL_EINVAL, "ORDERED needs an order array");
     if (la.mode == MANDEL_PLAN_LEARNED_LPT && !la.mlp)
         return fail(MANDEL_EINVAL, "LEARNED_LPT needs model parameters");
+    if (la.probe_cap == 0)
+        la.probe_cap = 128;
+    if (la.probe_cap < 1 || la.probe_cap > (1 << 20))
+        return fail(MANDEL_EINVAL, "probe_cap=%d outside [1, 2^20]", la.probe_cap);
     if (p->ntiles == 0)
         return MANDEL_OK;
     if (!out)
@@ -278,7 +283,7 @@ int mandel_plan_launch(mandel_plan *p, int32_t *out, const mandel_launch *args, 
 
     for (const GraphEntry &g : p->graphs) {
         if (g.out == out && g.mode == la.mode && g.order == la.order && g.mlp == la.mlp &&
-            g.tile_cost == la.tile_cost && g.stats == la.stats) {
+            g.tile_cost == la.tile_cost && g.stats == la.stats && g.probe_cap == la.probe_cap) {
             hipError_t e = hipGraphLaunch(g.exec, s);
             return e == hipSuccess ? MANDEL_OK : hip_fail(e, "hipGraphLaunch");
         }
@@ -290,6 +295,7 @@ int mandel_plan_launch(mandel_plan *p, int32_t *out, const mandel_launch *args, 
     g.mlp = la.mlp;
     g.tile_cost = la.tile_cost;
     g.stats = la.stats;
+    g.probe_cap = la.probe_cap;
     g.graph = nullptr;
     g.exec = nullptr;
     hipError_t e = hipStreamBeginCapture(p->capture, hipStreamCaptureModeThreadLocal);

@@ -65,7 +65,8 @@ class Tuning(ctypes.Structure):
 class LaunchC(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("use_graph", ctypes.c_int32),
                 ("order", ctypes.c_void_p), ("mlp", ctypes.c_void_p),
-                ("tile_cost", ctypes.c_void_p), ("stats", ctypes.c_void_p)]
+                ("tile_cost", ctypes.c_void_p), ("stats", ctypes.c_void_p),
+                ("probe_cap", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 PLAN_MODES = {"fcfs": 0, "ordered": 1, "probe": 2, "learned": 3}
@@ -252,9 +253,9 @@ class Plan:
         return max((o + v.m * v.n for o, v in zip(self.out_offsets, self.views)), default=0)
 
     def launch(self, out, mode="fcfs", use_graph=False, order=None, mlp=None, tile_cost=None,
-               stats=None, stream=None):
+               stats=None, probe_cap=0, stream=None):
         la = LaunchC(PLAN_MODES[mode] if isinstance(mode, str) else int(mode), int(use_graph),
-                     _ptr(order), _ptr(mlp), _ptr(tile_cost), _ptr(stats))
+                     _ptr(order), _ptr(mlp), _ptr(tile_cost), _ptr(stats), int(probe_cap), 0)
         check(lib().mandel_plan_launch(self._h, _ptr(out), ctypes.byref(la), _stream(stream)))
         return out
 
