@@ -97,7 +97,8 @@ typedef struct mandel_sched {
                                 0 = also allow deferred blocks of tests [0] */
     int32_t block_iters;     /* longest deferred-test block K, 1..1024 [256] */
     int32_t young_iters;     /* pixels younger than this are tested every update [8] */
-    int32_t reserved;
+    int32_t refill_lanes;    /* while updates are tested one by one, lanes whose pixel
+                                finished are refilled once this many are idle, 1..64 [16] */
     const int32_t *order;    /* device int32[ntiles], ORDERED_TILES only: a permutation */
     int64_t *tile_cost;      /* device int64[ntiles] or NULL: sum of counts per tile
                                 (tile policies; cleared by the call) */
@@ -151,7 +152,7 @@ typedef struct mandel_tuning {
     int32_t block_iters;     /* [256] */
     int32_t young_iters;     /* [8] */
     int32_t groups;          /* persistent workgroups [fill the device] */
-    int32_t reserved;
+    int32_t refill_lanes;    /* [16], as in mandel_sched */
 } mandel_tuning;
 
 typedef struct mandel_plan mandel_plan;

@@ -192,6 +192,10 @@ int check_sched(const mandel_sched *s, mandel_sched *o)
         d.young_iters = 8;
     if (d.young_iters < 0)
         return fail(MANDEL_EINVAL, "negative young_iters");
+    if (d.refill_lanes == 0)
+        d.refill_lanes = 16;
+    if (d.refill_lanes < 1 || d.refill_lanes > 64)
+        return fail(MANDEL_EINVAL, "refill_lanes=%d outside [1, 64]", d.refill_lanes);
     if (d.policy == MANDEL_ORDERED_TILES && !d.order)
         return fail(MANDEL_EINVAL, "ORDERED_TILES needs an order array");
     *o = d;
@@ -296,6 +300,7 @@ int mandel_render_sched(const mandel_window *w, int32_t m, int32_t n, int32_t ma
     a.ntiles = ntiles;
     a.block_iters = s.block_iters;
     a.young_iters = s.young_iters;
+    a.refill_lanes = s.refill_lanes;
     a.out = out;
     a.order = s.order;
     a.tile_cost = rows ? nullptr : s.tile_cost;

@@ -66,6 +66,7 @@ int fill_tuning(const mandel_tuning *t, mandel_tuning *o)
     s.waves_per_group = d.waves_per_group;
     s.block_iters = d.block_iters;
     s.young_iters = d.young_iters;
+    s.refill_lanes = d.refill_lanes;
     s.workers = d.groups;
     mandel_sched c;
     int rc = check_sched(&s, &c);
@@ -77,6 +78,7 @@ int fill_tuning(const mandel_tuning *t, mandel_tuning *o)
     d.waves_per_group = c.waves_per_group;
     d.block_iters = c.block_iters;
     d.young_iters = c.young_iters;
+    d.refill_lanes = c.refill_lanes;
     d.groups = c.workers;
     *o = d;
     return MANDEL_OK;
@@ -147,6 +149,7 @@ int enqueue(mandel_plan *p, int32_t *out, const mandel_launch &la, hipStream_t s
     a.ntiles = p->ntiles;
     a.block_iters = p->tune.block_iters;
     a.young_iters = p->tune.young_iters;
+    a.refill_lanes = p->tune.refill_lanes;
     a.out = out;
     a.head = p->d_head;
     a.order = order;

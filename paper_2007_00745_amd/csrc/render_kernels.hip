@@ -363,6 +363,7 @@ __global__ void __launch_bounds__(1024) render_kernel(RenderArgs a)
 
     const uint32_t K = (uint32_t)a.block_iters; // longest deferred block
     const uint32_t P = (uint32_t)a.young_iters;
+    const uint32_t R = (uint32_t)a.refill_lanes; // idle lanes that trigger a refill round
     const uint32_t Kmin = K < 8u ? K : 8u;
     uint32_t Kc = K; // current deferred block length (halved after a replay, doubled after a clean block)
 
@@ -452,6 +453,7 @@ __global__ void __launch_bounds__(1024) render_kernel(RenderArgs a)
                 climit = P;
         }
         uint32_t done = 0;
+        uint64_t cmask = amask; // lanes still active in this checked run
         for (;;) {
             const uint32_t W0 = W;
             const uint64_t m0 = tested_update();
@@ -459,7 +461,7 @@ __global__ void __launch_bounds__(1024) render_kernel(RenderArgs a)
             const uint64_t m2 = tested_update();
             const uint64_t m3 = tested_update();
             W += 4;
-            const uint64_t any = (m0 | m1 | m2 | m3) & amask;
+            const uint64_t any = (m0 | m1 | m2 | m3) & cmask;
             if (any != 0 || budget < 4) {
                 const uint32_t ke = ((m0 >> lane) & 1u) ? 0u
                                   : ((m1 >> lane) & 1u) ? 1u
@@ -477,6 +479,19 @@ __global__ void __launch_bounds__(1024) render_kernel(RenderArgs a)
                     acc += cnt;
                     active = false;
                     pending = false;
+                }
+                // Lazy refill: with budget >= 4 only escapes happened here; while few
+                // lanes are idle (or nothing is left to refill from) keep iterating
+                // instead of paying for a refill round.  budget - 4 stays a lower
+                // bound of every remaining lane's distance to its deadline.
+                if (budget >= 4) {
+                    cmask = ballot(active);
+                    if (cmask != 0 && ((uint32_t)__popcll(~cmask) < R || exhausted) &&
+                        (!DEFER || done + 4 < climit)) {
+                        budget -= 4;
+                        done += 4;
+                        continue;
+                    }
                 }
                 break;
             }

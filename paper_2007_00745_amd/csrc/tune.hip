@@ -76,6 +76,7 @@ extern "C" int mandel_plan_autotune(const mandel_view *views, int32_t nviews, in
     best->waves_per_group = 4;
     best->block_iters = 256;
     best->young_iters = 8;
+    best->refill_lanes = 16;
     if (work.empty())
         return MANDEL_OK;
     std::sort(work.begin(), work.end());
@@ -146,6 +147,7 @@ extern "C" int mandel_plan_autotune(const mandel_view *views, int32_t nviews, in
         t.waves_per_group = c.wpg;
         t.block_iters = 256;
         t.young_iters = 8;
+        t.refill_lanes = 16;
         mandel_plan *p = nullptr;
         rc = mandel_plan_create(sample.data(), (int32_t)sample.size(), &t, &p);
         if (rc)

@@ -54,6 +54,9 @@ SCHEDS = [
     dict(policy="fcfs", tile_w=128, tile_h=16, block_iters=7, young_iters=0),
     dict(policy="fcfs", block_iters=1, young_iters=1),
     dict(policy="fcfs", block_iters=1024, young_iters=0, waves_per_group=16),
+    dict(policy="fcfs", refill_lanes=1),
+    dict(policy="fcfs", refill_lanes=64, young_iters=32),
+    dict(policy="fcfs", check_every=1, refill_lanes=40),
     dict(policy="grid"),
     dict(policy="grid", check_every=1, tile_w=16, tile_h=16),
     dict(policy="static", workers=7),
