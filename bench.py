@@ -35,7 +35,7 @@ if ROOT not in sys.path:
 FP64_PEAK_TFLOPS = 78.6   # MI355X FP64 vector: 256 CU x 64 lanes x 2 (FMA) x 2.4 GHz
 FLOPS_PER_ITER = 7
 KERNEL_SRC = os.path.join(ROOT, "paper_2007_00745_amd", "csrc", "render_kernels.hip")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "render_fcfs_8192_traffic.txt")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "render_ordered_8192_traffic.txt")
 
 
 def log(msg):

@@ -103,7 +103,9 @@ typedef struct mandel_sched {
     int64_t *tile_cost;      /* device int64[ntiles] or NULL: sum of counts per tile
                                 (tile policies; cleared by the call) */
     int32_t *claims;         /* NULL, or a log cleared by the call: tile policies,
-                                device int32[ntiles], times each tile was claimed;
+                                device int32[ntiles], times a non-empty row part of
+                                each tile was claimed (min(tile_parts, rows of the
+                                tile) when every tile is rendered once);
                                 row policies, device int32[m], the sum of (worker + 1)
                                 over the takes of each row (a row taken once by
                                 worker r holds r + 1) */
@@ -114,6 +116,11 @@ typedef struct mandel_sched {
                                 ticks (hipDeviceAttributeWallClockRate): [4] first
                                 queue claim, [5] first claim that found the queue
                                 empty, [6] last wavefront exit (tile policies) */
+    int32_t tile_parts;      /* FCFS / ORDERED: each tile is queued as this many row
+                                parts (rows [p*h/parts, (p+1)*h/parts) of an h-row
+                                tile), so one expensive tile can be shared by several
+                                wavefronts; 1..64 [1]; GRID ignores it */
+    int32_t reserved;
 } mandel_sched;
 
 /*
@@ -153,6 +160,8 @@ typedef struct mandel_tuning {
     int32_t young_iters;     /* [8] */
     int32_t groups;          /* persistent workgroups [fill the device] */
     int32_t refill_lanes;    /* [16], as in mandel_sched */
+    int32_t tile_parts;      /* [1], as in mandel_sched */
+    int32_t reserved;
 } mandel_tuning;
 
 typedef struct mandel_plan mandel_plan;

@@ -196,6 +196,12 @@ int check_sched(const mandel_sched *s, mandel_sched *o)
         d.refill_lanes = 16;
     if (d.refill_lanes < 1 || d.refill_lanes > 64)
         return fail(MANDEL_EINVAL, "refill_lanes=%d outside [1, 64]", d.refill_lanes);
+    if (d.tile_parts == 0)
+        d.tile_parts = 1;
+    if (d.tile_parts < 1 || d.tile_parts > 64)
+        return fail(MANDEL_EINVAL, "tile_parts=%d outside [1, 64]", d.tile_parts);
+    if (d.policy == MANDEL_GRID_TILES)
+        d.tile_parts = 1;
     if (d.policy == MANDEL_ORDERED_TILES && !d.order)
         return fail(MANDEL_EINVAL, "ORDERED_TILES needs an order array");
     *o = d;
@@ -301,6 +307,7 @@ int mandel_render_sched(const mandel_window *w, int32_t m, int32_t n, int32_t ma
     a.block_iters = s.block_iters;
     a.young_iters = s.young_iters;
     a.refill_lanes = s.refill_lanes;
+    a.parts = s.tile_parts;
     a.out = out;
     a.order = s.order;
     a.tile_cost = rows ? nullptr : s.tile_cost;

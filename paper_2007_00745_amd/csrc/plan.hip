@@ -67,6 +67,7 @@ int fill_tuning(const mandel_tuning *t, mandel_tuning *o)
     s.block_iters = d.block_iters;
     s.young_iters = d.young_iters;
     s.refill_lanes = d.refill_lanes;
+    s.tile_parts = d.tile_parts;
     s.workers = d.groups;
     mandel_sched c;
     int rc = check_sched(&s, &c);
@@ -79,6 +80,7 @@ int fill_tuning(const mandel_tuning *t, mandel_tuning *o)
     d.block_iters = c.block_iters;
     d.young_iters = c.young_iters;
     d.refill_lanes = c.refill_lanes;
+    d.tile_parts = c.tile_parts;
     d.groups = c.workers;
     *o = d;
     return MANDEL_OK;
@@ -150,6 +152,7 @@ int enqueue(mandel_plan *p, int32_t *out, const mandel_launch &la, hipStream_t s
     a.block_iters = p->tune.block_iters;
     a.young_iters = p->tune.young_iters;
     a.refill_lanes = p->tune.refill_lanes;
+    a.parts = p->tune.tile_parts;
     a.out = out;
     a.head = p->d_head;
     a.order = order;

@@ -37,6 +37,7 @@ struct RenderArgs {
     int32_t block_iters;           // K: updates per deferred block
     int32_t young_iters;           // P: pixels younger than P updates are tested every update
     int32_t refill_lanes;          // checked mode refills once this many lanes are idle
+    int32_t parts;                 // queue items per tile (row parts), >= 1; 1 for GRID
     int32_t *out;                  // output base
     unsigned long long *head;      // queue head (FCFS / ORDERED)
     const int32_t *order;          // ORDERED: queue slot -> tile id

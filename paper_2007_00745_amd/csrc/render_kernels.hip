@@ -154,8 +154,10 @@ __global__ void __launch_bounds__(1024) render_kernel(RenderArgs a)
     auto next_item = [&]() -> bool {
         if constexpr (POLICY == POLICY_FCFS_TILES || POLICY == POLICY_ORDERED_TILES ||
                       POLICY == POLICY_GRID_TILES) {
+            const int64_t nslots = POLICY == POLICY_GRID_TILES ? a.ntiles : a.ntiles * a.parts;
             for (;;) {
                 int64_t t;
+                int32_t part = 0;
                 if constexpr (POLICY == POLICY_GRID_TILES) {
                     if (grid_done)
                         return false;
@@ -173,28 +175,29 @@ __global__ void __launch_bounds__(1024) render_kernel(RenderArgs a)
                             if (qb == 0)
                                 atomicMin((unsigned long long *)&a.stats[4],
                                           (unsigned long long)wall_clock64());
-                            if (qb >= a.ntiles && qb < a.ntiles + a.grain)
+                            if (qb >= nslots && qb < nslots + a.grain)
                                 atomicMin((unsigned long long *)&a.stats[5],
                                           (unsigned long long)wall_clock64());
                         }
-                        if (qb >= a.ntiles)
+                        if (qb >= nslots)
                             return false;
                         q_next = qb;
-                        int64_t left = a.ntiles - qb;
+                        int64_t left = nslots - qb;
                         q_left = (int32_t)(left < a.grain ? left : a.grain);
                     }
-                    int64_t slot = q_next++;
+                    const int64_t slot = q_next++;
                     --q_left;
+                    // slot = item * parts + part: the queue hands out row parts of tiles
+                    const int64_t item = a.parts == 1 ? slot : slot / a.parts;
+                    part = (int32_t)(slot - item * a.parts);
                     if constexpr (POLICY == POLICY_ORDERED_TILES) {
-                        t = (int64_t)a.order[slot];
+                        t = (int64_t)a.order[item];
                         if (t < 0 || t >= a.ntiles)
                             continue; // not a tile id: skipped, never dereferenced
                     } else {
-                        t = slot;
+                        t = item;
                     }
                 }
-                if (a.claims && lane == 0)
-                    atomicAdd(&a.claims[t], 1);
                 int32_t v = 0;
                 int64_t tile_off;
                 int32_t tiles_x, vm, vn;
@@ -216,14 +219,21 @@ __global__ void __launch_bounds__(1024) render_kernel(RenderArgs a)
                 int32_t x0 = tx * a.tile_w, y0 = ty * a.tile_h;
                 int32_t w = vn - x0 < a.tile_w ? vn - x0 : a.tile_w;
                 int32_t h = vm - y0 < a.tile_h ? vm - y0 : a.tile_h;
+                // rows [r0, r1) of the tile form this part
+                const int32_t r0 = (int32_t)(((int64_t)part * h) / a.parts);
+                const int32_t r1 = (int32_t)(((int64_t)(part + 1) * h) / a.parts);
+                if (r1 <= r0)
+                    continue; // empty part (a tile with fewer rows than parts)
+                if (a.claims && lane == 0)
+                    atomicAdd(&a.claims[t], 1);
                 s_view = v;
                 s_x0 = x0;
-                s_y0 = y0;
+                s_y0 = y0 + r0;
                 s_w = w;
                 s_next = 0;
                 s_in = 0;
                 s_jn = 0;
-                s_cnt = w * h;
+                s_cnt = w * (r1 - r0);
                 s_tile = t;
                 ++taken;
                 return true;

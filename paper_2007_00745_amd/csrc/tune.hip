@@ -34,13 +34,14 @@ uint64_t bits(double d)
 }
 
 struct Candidate {
-    int32_t tw, th, grain, wpg;
+    int32_t tw, th, grain, wpg, parts;
 };
 
 const Candidate kCandidates[] = {
-    {64, 8, 1, 4},  {32, 8, 1, 4},  {64, 4, 1, 4},  {32, 4, 1, 4},  {128, 4, 1, 4},
-    {16, 16, 1, 4}, {64, 16, 1, 4}, {128, 8, 1, 4}, {64, 8, 4, 4},  {32, 8, 4, 4},
-    {64, 4, 4, 4},  {64, 8, 1, 1},  {32, 8, 1, 1},  {64, 4, 1, 1},  {32, 4, 2, 8},
+    {64, 8, 1, 4, 1},  {32, 8, 1, 4, 1},  {64, 4, 1, 4, 1},  {32, 4, 1, 4, 1},
+    {128, 4, 1, 4, 1}, {16, 16, 1, 4, 1}, {64, 16, 1, 4, 4}, {128, 8, 1, 4, 2},
+    {64, 8, 4, 4, 1},  {64, 8, 1, 4, 4},  {64, 8, 1, 4, 2},  {64, 8, 1, 1, 1},
+    {32, 8, 1, 1, 1},  {64, 4, 1, 1, 1},  {32, 4, 2, 8, 1},
 };
 
 } // namespace
@@ -77,6 +78,7 @@ extern "C" int mandel_plan_autotune(const mandel_view *views, int32_t nviews, in
     best->block_iters = 256;
     best->young_iters = 8;
     best->refill_lanes = 16;
+    best->tile_parts = 1;
     if (work.empty())
         return MANDEL_OK;
     std::sort(work.begin(), work.end());
@@ -148,6 +150,7 @@ extern "C" int mandel_plan_autotune(const mandel_view *views, int32_t nviews, in
         t.block_iters = 256;
         t.young_iters = 8;
         t.refill_lanes = 16;
+        t.tile_parts = c.parts;
         mandel_plan *p = nullptr;
         rc = mandel_plan_create(sample.data(), (int32_t)sample.size(), &t, &p);
         if (rc)

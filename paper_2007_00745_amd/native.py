@@ -43,7 +43,8 @@ class Sched(ctypes.Structure):
                 ("check_every", ctypes.c_int32), ("block_iters", ctypes.c_int32),
                 ("young_iters", ctypes.c_int32), ("refill_lanes", ctypes.c_int32),
                 ("order", ctypes.c_void_p), ("tile_cost", ctypes.c_void_p),
-                ("claims", ctypes.c_void_p), ("stats", ctypes.c_void_p)]
+                ("claims", ctypes.c_void_p), ("stats", ctypes.c_void_p),
+                ("tile_parts", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class ViewC(ctypes.Structure):
@@ -56,10 +57,11 @@ class Tuning(ctypes.Structure):
     _fields_ = [("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32),
                 ("grain", ctypes.c_int32), ("waves_per_group", ctypes.c_int32),
                 ("block_iters", ctypes.c_int32), ("young_iters", ctypes.c_int32),
-                ("groups", ctypes.c_int32), ("refill_lanes", ctypes.c_int32)]
+                ("groups", ctypes.c_int32), ("refill_lanes", ctypes.c_int32),
+                ("tile_parts", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
-        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+        return {k: int(getattr(self, k)) for k, _ in self._fields_ if k != "reserved"}
 
 
 class LaunchC(ctypes.Structure):
@@ -187,11 +189,11 @@ def render(window, m: int, n: int, max_iter: int, R: float, out=None, stream=Non
 
 def make_sched(policy="fcfs", tile_w=0, tile_h=0, grain=0, workers=0, waves_per_group=0,
                check_every=0, block_iters=0, young_iters=0, refill_lanes=0, order=None,
-               tile_cost=None, claims=None, stats=None) -> Sched:
+               tile_cost=None, claims=None, stats=None, tile_parts=0) -> Sched:
     pol = POLICIES[policy] if isinstance(policy, str) else int(policy)
     return Sched(pol, tile_w, tile_h, grain, workers, waves_per_group, check_every,
                  block_iters, young_iters, refill_lanes, _ptr(order), _ptr(tile_cost),
-                 _ptr(claims), _ptr(stats))
+                 _ptr(claims), _ptr(stats), tile_parts, 0)
 
 
 def render_sched(window, m: int, n: int, max_iter: int, R: float, out=None, stream=None,

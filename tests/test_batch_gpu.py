@@ -48,7 +48,8 @@ def _params(seed, feat=None):
 
 
 @pytest.mark.parametrize("tuning", [{}, dict(tile_w=32, tile_h=4, grain=3),
-                                    dict(tile_w=16, tile_h=16, waves_per_group=1, groups=37)])
+                                    dict(tile_w=16, tile_h=16, waves_per_group=1, groups=37),
+                                    dict(tile_parts=4, grain=2), dict(tile_h=5, tile_parts=8)])
 def test_plan_fcfs(small_batch, tuning):
     views, want = small_batch
     plan = native.Plan(views, tuning)
@@ -60,9 +61,10 @@ def test_plan_fcfs(small_batch, tuning):
     plan.close()
 
 
-def test_plan_modes_and_graph_replays(small_batch):
+@pytest.mark.parametrize("parts", [1, 4])
+def test_plan_modes_and_graph_replays(small_batch, parts):
     views, want = small_batch
-    plan = native.Plan(views)
+    plan = native.Plan(views, dict(tile_parts=parts))
     nt = plan.ntiles
     feat = plan.features()
     params = torch.tensor(_params(3, feat), dtype=torch.float32, device="cuda")

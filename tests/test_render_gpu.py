@@ -57,6 +57,9 @@ SCHEDS = [
     dict(policy="fcfs", refill_lanes=1),
     dict(policy="fcfs", refill_lanes=64, young_iters=32),
     dict(policy="fcfs", check_every=1, refill_lanes=40),
+    dict(policy="fcfs", tile_parts=4),
+    dict(policy="fcfs", tile_h=3, tile_parts=8, grain=5),
+    dict(policy="grid", tile_parts=4),
     dict(policy="grid"),
     dict(policy="grid", check_every=1, tile_w=16, tile_h=16),
     dict(policy="static", workers=7),
@@ -88,15 +91,21 @@ def test_c1_ordered_permutations(c1_ref):
 def test_claims_and_costs(c1_ref):
     # every tile claimed exactly once; per-tile cost log equals the sum of its counts
     v = workloads.c1()
-    for tw, th, g in ((64, 8, 1), (48, 5, 4), (640, 1, 2)):
+    for tw, th, g, parts in ((64, 8, 1, 1), (48, 5, 4, 1), (640, 1, 2, 1), (64, 8, 3, 4),
+                             (32, 5, 1, 8)):
         nt = native.tile_count(v.m, v.n, tw, th)
         claims = torch.full((nt,), 7, dtype=torch.int32, device="cuda")
         cost = torch.full((nt,), -1, dtype=torch.int64, device="cuda")
         stats = torch.zeros(8, dtype=torch.int64, device="cuda")
         got = gpu_render(v, tile_w=tw, tile_h=th, grain=g, claims=claims, tile_cost=cost,
-                         stats=stats)
+                         stats=stats, tile_parts=parts)
         assert np.array_equal(got, c1_ref)
-        assert torch.all(claims == 1)
+        # every non-empty part of every tile claimed exactly once
+        rows = np.minimum(th, v.m - np.arange(0, v.m, th))
+        want_parts = np.array([sum(1 for p in range(parts) if ((p + 1) * h) // parts > (p * h) // parts)
+                               for h in rows])
+        assert np.array_equal(claims.cpu().numpy().reshape(len(rows), -1),
+                              np.repeat(want_parts[:, None], -(-v.n // tw), axis=1))
         ty, tx = -(-v.m // th), -(-v.n // tw)
         pad = np.zeros((ty * th, tx * tw), dtype=np.int64)
         pad[:v.m, :v.n] = c1_ref
@@ -104,7 +113,7 @@ def test_claims_and_costs(c1_ref):
         assert np.array_equal(cost.cpu().numpy(), want)
         st = stats.cpu().numpy()
         assert st[1] == c1_ref.sum()
-        assert st[3] == nt
+        assert st[3] == int(want_parts.sum()) * (-(-v.n // tw))
         assert st[0] * 64 >= st[1]  # lane iterations cannot exceed lane slots
 
 
