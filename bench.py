@@ -208,6 +208,51 @@ def comparisons(torch, native, view, plan, out, cost, sum_counts, stream) -> dic
     return comp
 
 
+FP32_PEAK_TFLOPS = 157.3  # MI355X FP32 vector (FMA = 2 flops)
+HBM_PEAK_GBS = 8000.0
+
+
+def secondary_kernels(torch, native, plan, params, sum_probe_iters, reps: int) -> dict:
+    """Each ordering kernel timed alone (events on the launching stream) against
+    the roofline that bounds it: probe features (FP64 VALU), cost-model inference
+    and one training step (FP32 VALU), the bucket order (HBM)."""
+    import numpy as np
+    nt = plan.ntiles
+    res = {}
+    feat = plan.features()
+    ms = timed_ms(torch, lambda: plan.features(feat), reps, "features kernel")
+    tflops = 7 * sum_probe_iters / (ms / 1e3) / 1e12
+    res["features"] = {"ms": ms, "tiles": nt, "probe_iterations": sum_probe_iters,
+                       "bound": "alu", "achieved_tflops_fp64": tflops,
+                       "frac": tflops / FP64_PEAK_TFLOPS}
+    keys = torch.empty(nt, dtype=torch.float32, device="cuda")
+    ms = timed_ms(torch, lambda: native.mlp_forward(params, feat, keys), reps, "mlp forward")
+    flops = nt * 2 * (68 * 64 + 64 * 64 + 64)
+    res["mlp_forward"] = {"ms": ms, "flops": flops, "bound": "alu",
+                          "achieved_tflops_fp32": flops / (ms / 1e3) / 1e12,
+                          "frac": flops / (ms / 1e3) / 1e12 / FP32_PEAK_TFLOPS}
+    perm = torch.empty(nt, dtype=torch.int32, device="cuda")
+    ms = timed_ms(torch, lambda: native.order_desc(keys, perm), reps, "order")
+    nbytes = nt * (4 + 4 + 4)  # keys read twice, permutation written once
+    res["order"] = {"ms": ms, "bytes": nbytes, "bound": "hbm",
+                    "achieved_gbs": nbytes / (ms / 1e3) / 1e9,
+                    "frac": nbytes / (ms / 1e3) / 1e9 / HBM_PEAK_GBS}
+    B = 512
+    p2 = params.clone()
+    m = torch.zeros_like(p2)
+    v = torch.zeros_like(p2)
+    target = torch.zeros(nt, dtype=torch.float32, device="cuda")
+    idx = torch.arange(B, dtype=torch.int32, device="cuda")
+    work = torch.empty(native.mlp_work_floats(B), dtype=torch.float32, device="cuda")
+    ms = timed_ms(torch, lambda: native.mlp_train_step(p2, m, v, 1, feat, target, idx, 1e-3,
+                                                       work=work), reps, "train step")
+    flops = B * 3 * 2 * (68 * 64 + 64 * 64 + 64)  # forward + two backward products
+    res["mlp_train_step"] = {"ms": ms, "batch": B, "flops": flops, "bound": "alu",
+                             "achieved_tflops_fp32": flops / (ms / 1e3) / 1e12,
+                             "frac": flops / (ms / 1e3) / 1e12 / FP32_PEAK_TFLOPS}
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -305,9 +350,15 @@ def main():
     render_tflops = FLOPS_PER_ITER * sum_counts / (render_ms / 1e3) / 1e12
     log(f"bench: ordered render alone {render_ms:.3f} ms, {render_tflops:.2f} TFLOP/s")
     comp = None
+    kernels = None
     if not args.profile:
         comp = comparisons(torch, native, view, plan, out, cost, sum_counts, stream)
         comp["render_kernel_ms"] = render_ms
+        import numpy as np
+        f = plan.features().cpu().numpy()[:, 4:].astype(np.float64)
+        cap = min(view.max_iter, 128)
+        probe_iters = int(np.rint(np.exp(f * np.log1p(cap)) - 1).sum())
+        kernels = secondary_kernels(torch, native, plan, params, probe_iters, 3)
 
     if args.copy_calibration:
         a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
@@ -351,6 +402,7 @@ def main():
         "kernel_source_sha256_16": kernel_sha(),
         "cost_model": cm_info,
         "comparisons": comp,
+        "secondary_kernels": kernels,
     }
     if not args.no_makespan:
         res["makespan"] = makespans(torch, native, workloads, costmodel, args.makespan_reps,

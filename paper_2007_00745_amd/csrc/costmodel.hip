@@ -158,113 +158,127 @@ __global__ void __launch_bounds__(256) mlp_forward_kernel(const float *params, c
 
 // ---- MLP training ------------------------------------------------------------
 // work layout (floats): A1[B][64] | A2[B][64] | gy[B] | err[B] | gA1[B][64] | gA2[B][64]
-__global__ void __launch_bounds__(256) train_forward_kernel(const float *params, const float *x,
+//                       | partial[GSLICES][NTRAIN]
+constexpr int GSLICES = 16; // the minibatch is split into this many slices for gradient sums
+
+__device__ __forceinline__ float lane_value(float v, int l)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+
+__device__ __forceinline__ float wave_sum_f(float v)
+{
+    for (int off = 32; off >= 1; off >>= 1)
+        v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// One wavefront per sample, lane o = hidden unit o: forward pass with saved
+// pre-activations, output error, and backpropagation to both hidden layers.
+__global__ void __launch_bounds__(256) train_fwd_bwd_kernel(const float *params, const float *x,
                                                             const float *target,
                                                             const int32_t *idx, int32_t B,
                                                             float *work)
 {
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    const int b = blockIdx.x * (blockDim.x / 64) + (threadIdx.x / 64);
     if (b >= B)
-        return;
+        return; // whole wavefronts leave together
+    const int o = threadIdx.x & 63;
     float *A1 = work, *A2 = work + (size_t)B * NH, *gy = work + (size_t)2 * B * NH;
     float *err = gy + B;
+    float *gA1 = work + (size_t)2 * B * NH + 2 * (size_t)B;
+    float *gA2 = gA1 + (size_t)B * NH;
     const int64_t row = idx[b];
     const float *xr = x + row * NF;
-    float h[NH];
-#pragma unroll
-    for (int o = 0; o < NH; ++o)
-        h[o] = params[OFF_B1 + o];
+    float a1 = params[OFF_B1 + o];
     for (int i = 0; i < NF; ++i) {
         const float xi = (xr[i] - params[OFF_MU + i]) * params[OFF_ISD + i];
-#pragma unroll
-        for (int o = 0; o < NH; ++o)
-            h[o] = fmaf(params[OFF_W1 + o * NF + i], xi, h[o]);
+        a1 = fmaf(params[OFF_W1 + o * NF + i], xi, a1);
     }
-#pragma unroll
-    for (int o = 0; o < NH; ++o) {
-        A1[(size_t)b * NH + o] = h[o];
-        h[o] = fmaxf(h[o], 0.0f);
-    }
-    float out = params[OFF_B3];
-    for (int o = 0; o < NH; ++o) {
-        float a = params[OFF_B2 + o];
-#pragma unroll
-        for (int i = 0; i < NH; ++i)
-            a = fmaf(params[OFF_W2 + o * NH + i], h[i], a);
-        A2[(size_t)b * NH + o] = a;
-        out = fmaf(params[OFF_W3 + o], fmaxf(a, 0.0f), out);
-    }
-    const float e = out - target[row];
+    const float h1 = fmaxf(a1, 0.0f);
+    float a2 = params[OFF_B2 + o];
+    for (int i = 0; i < NH; ++i)
+        a2 = fmaf(params[OFF_W2 + o * NH + i], lane_value(h1, i), a2);
+    const float w3o = params[OFF_W3 + o];
+    const float y = params[OFF_B3] + wave_sum_f(w3o * fmaxf(a2, 0.0f));
+    const float e = y - target[row];
     const float g = 2.0f * e / (float)B;
-    gy[b] = g;
-    err[b] = e * e;
-    float *gA2 = work + (size_t)3 * B * NH + 2 * (size_t)B;
-    for (int o = 0; o < NH; ++o)
-        gA2[(size_t)b * NH + o] = A2[(size_t)b * NH + o] > 0.0f ? g * params[OFF_W3 + o] : 0.0f;
+    const float ga2 = a2 > 0.0f ? g * w3o : 0.0f;
+    float gh1 = 0.0f;
+    for (int k = 0; k < NH; ++k)
+        gh1 = fmaf(lane_value(ga2, k), params[OFF_W2 + k * NH + o], gh1);
+    A1[(size_t)b * NH + o] = a1;
+    A2[(size_t)b * NH + o] = a2;
+    gA2[(size_t)b * NH + o] = ga2;
+    gA1[(size_t)b * NH + o] = a1 > 0.0f ? gh1 : 0.0f;
+    if (o == 0) {
+        gy[b] = g;
+        err[b] = e * e;
+    }
 }
 
-// gA1[b][i] = relu'(A1[b][i]) * sum_o gA2[b][o] W2[o][i],  gA2[b][o] = gy[b] w3[o] relu'(A2[b][o])
-__global__ void __launch_bounds__(256) train_hidden_kernel(const float *params, int32_t B,
-                                                           float *work)
-{
-    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= (int64_t)B * NH)
-        return;
-    const int b = (int)(q / NH), i = (int)(q % NH);
-    const float *A1 = work;
-    float *gA1 = work + (size_t)2 * B * NH + 2 * (size_t)B;
-    const float *gA2 = gA1 + (size_t)B * NH;
-    float s = 0.0f;
-    for (int o = 0; o < NH; ++o)
-        s += gA2[(size_t)b * NH + o] * params[OFF_W2 + o * NH + i];
-    gA1[q] = A1[q] > 0.0f ? s : 0.0f;
-}
-
-// One thread per trainable parameter: its gradient (sum over the minibatch),
-// then the Adam update.
-__global__ void __launch_bounds__(256) train_grad_adam_kernel(float *params, float *m, float *v,
-                                                              const float *x, const int32_t *idx,
-                                                              int32_t B, const float *work,
-                                                              float lr, float bc1, float bc2)
+// Partial gradient of trainable parameter j over slice blockIdx.y of the minibatch.
+__global__ void __launch_bounds__(256) train_grad_partial_kernel(const float *params,
+                                                                 const float *x,
+                                                                 const int32_t *idx, int32_t B,
+                                                                 float *work)
 {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= NTRAIN)
         return;
+    const int sl = blockIdx.y;
+    const int per = (B + GSLICES - 1) / GSLICES;
+    const int b0 = sl * per, b1 = b0 + per < B ? b0 + per : B;
     const float *A1 = work, *A2 = work + (size_t)B * NH, *gy = work + (size_t)2 * B * NH;
     const float *gA1 = work + (size_t)2 * B * NH + 2 * (size_t)B;
     const float *gA2 = gA1 + (size_t)B * NH;
+    float *partial = work + (size_t)4 * B * NH + 2 * (size_t)B;
     const int p = MANDEL_MLP_NORM + j;
     float g = 0.0f;
     if (p < OFF_B1) { // W1[o][i]
         const int o = (p - OFF_W1) / NF, i = (p - OFF_W1) % NF;
         const float mu = params[OFF_MU + i], isd = params[OFF_ISD + i];
-        for (int b = 0; b < B; ++b) {
+        for (int b = b0; b < b1; ++b) {
             const float xi = (x[(int64_t)idx[b] * NF + i] - mu) * isd;
-            g += gA1[(size_t)b * NH + o] * xi;
+            g = fmaf(gA1[(size_t)b * NH + o], xi, g);
         }
     } else if (p < OFF_W2) { // b1[o]
         const int o = p - OFF_B1;
-        for (int b = 0; b < B; ++b)
+        for (int b = b0; b < b1; ++b)
             g += gA1[(size_t)b * NH + o];
     } else if (p < OFF_B2) { // W2[o][i]
         const int o = (p - OFF_W2) / NH, i = (p - OFF_W2) % NH;
-        for (int b = 0; b < B; ++b)
-            g += gA2[(size_t)b * NH + o] * fmaxf(A1[(size_t)b * NH + i], 0.0f);
+        for (int b = b0; b < b1; ++b)
+            g = fmaf(gA2[(size_t)b * NH + o], fmaxf(A1[(size_t)b * NH + i], 0.0f), g);
     } else if (p < OFF_W3) { // b2[o]
         const int o = p - OFF_B2;
-        for (int b = 0; b < B; ++b)
+        for (int b = b0; b < b1; ++b)
             g += gA2[(size_t)b * NH + o];
     } else if (p < OFF_B3) { // w3[o]
         const int o = p - OFF_W3;
-        for (int b = 0; b < B; ++b)
-            g += gy[b] * fmaxf(A2[(size_t)b * NH + o], 0.0f);
+        for (int b = b0; b < b1; ++b)
+            g = fmaf(gy[b], fmaxf(A2[(size_t)b * NH + o], 0.0f), g);
     } else { // b3
-        for (int b = 0; b < B; ++b)
+        for (int b = b0; b < b1; ++b)
             g += gy[b];
     }
-    // Adam (Kingma & Ba): moments, bias correction, step.  The gradients read
-    // only saved activations and the (untrained) standardisation, never a
-    // parameter that this launch updates.
+    partial[(size_t)sl * NTRAIN + j] = g;
+}
+
+// Sum of the slice partials, then Adam (Kingma & Ba): moments, bias correction,
+// step.  Gradients were formed from saved activations before any update.
+__global__ void __launch_bounds__(256) train_adam_kernel(float *params, float *m, float *v,
+                                                         int32_t B, const float *work, float lr,
+                                                         float bc1, float bc2)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= NTRAIN)
+        return;
+    const float *partial = work + (size_t)4 * B * NH + 2 * (size_t)B;
+    float g = 0.0f;
+    for (int sl = 0; sl < GSLICES; ++sl)
+        g += partial[(size_t)sl * NTRAIN + j];
+    const int p = MANDEL_MLP_NORM + j;
     const float mj = 0.9f * m[p] + 0.1f * g;
     const float vj = 0.999f * v[p] + 0.001f * g * g;
     m[p] = mj;
@@ -429,20 +443,40 @@ __global__ void __launch_bounds__(1024) scan_kernel(const uint32_t *hist, uint32
         cursor[t * PER + k] = base + loc[k];
 }
 
-__global__ void scatter_kernel(const float *keys, int64_t n, uint32_t *cursor, int32_t *perm)
+// Positions: each wavefront reserves, per distinct bucket, a range of the
+// workgroup's count for that bucket (LDS atomics); after a barrier the first
+// reserver of each bucket takes the workgroup's whole range from the global
+// cursor (one global atomic per bucket per workgroup).
+__global__ void __launch_bounds__(1024) scatter_kernel(const float *keys, int64_t n,
+                                                       uint32_t *cursor, int32_t *perm)
 {
+    __shared__ uint32_t cnt[NB];
+    __shared__ uint32_t base[NB];
+    for (int q = threadIdx.x; q < NB; q += blockDim.x)
+        cnt[q] = 0u;
+    __syncthreads();
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int lane = threadIdx.x & 63;
     const bool valid = t < n;
     const int b = valid ? bucket_of(keys[t]) : 0;
+    uint32_t my_off = 0;
+    bool first = false;
     per_distinct_bucket(valid, b, [&](int lb, uint64_t same, int leader) {
-        uint32_t base = 0;
+        uint32_t off = 0;
         if (lane == leader)
-            base = atomicAdd(&cursor[lb], (uint32_t)__popcll(same));
-        base = (uint32_t)__shfl((int)base, leader, 64);
+            off = atomicAdd(&cnt[lb], (uint32_t)__popcll(same));
+        off = (uint32_t)__shfl((int)off, leader, 64);
         if ((same >> lane) & 1u)
-            perm[base + lanes_below(same)] = (int32_t)t;
+            my_off = off + lanes_below(same);
+        if (lane == leader && off == 0u)
+            first = true;
     });
+    __syncthreads();
+    if (first)
+        base[b] = atomicAdd(&cursor[b], cnt[b]);
+    __syncthreads();
+    if (valid)
+        perm[base[b] + my_off] = (int32_t)t;
 }
 
 unsigned blocks_for(int64_t n, int threads, int64_t cap = 1 << 30)
@@ -488,7 +522,7 @@ hipError_t launch_order_desc(const float *keys, int64_t n, int32_t *perm, uint32
     hipLaunchKernelGGL(hist_kernel, dim3(blocks_for(n, 1024, 256)), dim3(1024), 0, s, keys, n,
                        hist);
     hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, s, hist, hist + NB);
-    hipLaunchKernelGGL(scatter_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, keys, n,
+    hipLaunchKernelGGL(scatter_kernel, dim3(blocks_for(n, 1024)), dim3(1024), 0, s, keys, n,
                        hist + NB, perm);
     return hipGetLastError();
 }
@@ -499,14 +533,14 @@ hipError_t launch_mlp_train_step(float *params, float *m, float *v, int32_t t, c
 {
     const double bc1 = 1.0 - std::pow(0.9, (double)t);
     const double bc2 = 1.0 - std::pow(0.999, (double)t);
-    hipLaunchKernelGGL(train_forward_kernel, dim3(blocks_for(B, 256)), dim3(256), 0, s, params,
-                       x, target, idx, B, work);
-    hipLaunchKernelGGL(train_hidden_kernel, dim3(blocks_for((int64_t)B * NH, 256)), dim3(256), 0,
-                       s, params, B, work);
+    hipLaunchKernelGGL(train_fwd_bwd_kernel, dim3(blocks_for(B, 4)), dim3(256), 0, s, params, x,
+                       target, idx, B, work);
     if (loss)
         hipLaunchKernelGGL(train_loss_kernel, dim3(1), dim3(256), 0, s, B, work, loss);
-    hipLaunchKernelGGL(train_grad_adam_kernel, dim3(blocks_for(NTRAIN, 256)), dim3(256), 0, s,
-                       params, m, v, x, idx, B, work, lr, (float)bc1, (float)bc2);
+    hipLaunchKernelGGL(train_grad_partial_kernel, dim3(blocks_for(NTRAIN, 256), GSLICES),
+                       dim3(256), 0, s, params, x, idx, B, work);
+    hipLaunchKernelGGL(train_adam_kernel, dim3(blocks_for(NTRAIN, 256)), dim3(256), 0, s, params,
+                       m, v, B, work, lr, (float)bc1, (float)bc2);
     return hipGetLastError();
 }
 
@@ -533,7 +567,7 @@ int64_t mandel_mlp_work_floats(int32_t batch)
 {
     if (batch < 1)
         return 0;
-    return (int64_t)batch * (4 * NH + 2);
+    return (int64_t)batch * (4 * NH + 2) + (int64_t)GSLICES * NTRAIN;
 }
 
 int mandel_mlp_train_step(float *params, float *adam_m, float *adam_v, int32_t t, const float *x,
