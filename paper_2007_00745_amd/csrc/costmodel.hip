@@ -55,9 +55,9 @@ __global__ void __launch_bounds__(256) features_kernel(const ViewDesc *views, in
     const int lane = threadIdx.x & 63;
     const int32_t v = find_view_b(views, nviews, t);
     const ViewDesc vd = views[v];
-    const int64_t lt = t - vd.tile_off;
-    const int32_t ty = (int32_t)(lt / vd.tiles_x);
-    const int32_t tx = (int32_t)(lt - (int64_t)ty * vd.tiles_x);
+    const int32_t lt = (int32_t)(t - vd.tile_off); // a plan has fewer than 2^31 tiles
+    const int32_t ty = lt / vd.tiles_x;
+    const int32_t tx = lt - ty * vd.tiles_x;
     const int32_t x0 = tx * tile_w, y0 = ty * tile_h;
     const int32_t w = vd.n - x0 < tile_w ? vd.n - x0 : tile_w;
     const int32_t h = vd.m - y0 < tile_h ? vd.m - y0 : tile_h;
@@ -96,7 +96,7 @@ __global__ void __launch_bounds__(256) features_kernel(const ViewDesc *views, in
         else if (lane == 1)
             val = (float)(vd.cy0 + (((double)y0 + 0.5 * (double)h) - 0.5 * (double)vd.m) * vd.dy);
         else if (lane == 2)
-            val = (float)log10((double)w * vd.dx);
+            val = log10f((float)((double)w * vd.dx));
         else
             val = logf((float)vd.max_iter);
         f[lane] = val;
