@@ -351,7 +351,16 @@ def main():
     log(f"bench: ordered render alone {render_ms:.3f} ms, {render_tflops:.2f} TFLOP/s")
     comp = None
     kernels = None
+    ceiling = None
     if not args.profile:
+        # measured FP64 ceilings: fma chains, and the bare update loop (no test, no scheduling)
+        ceiling = {"fma_chain": native.fp64_probe(0), "update_loop": native.fp64_probe(1),
+                   "update_loop_2_pixels_per_lane": native.fp64_probe(2)}
+        best = max(ceiling["update_loop"]["tflops"],
+                   ceiling["update_loop_2_pixels_per_lane"]["tflops"])
+        ceiling["render_frac_of_update_loop"] = render_tflops / best
+        log(f"bench: fp64 ceilings fma {ceiling['fma_chain']['tflops']:.1f}, update loop "
+            f"{best:.1f} TFLOP/s")
         comp = comparisons(torch, native, view, plan, out, cost, sum_counts, stream)
         comp["render_kernel_ms"] = render_ms
         import numpy as np
@@ -403,6 +412,7 @@ def main():
         "cost_model": cm_info,
         "comparisons": comp,
         "secondary_kernels": kernels,
+        "fp64_ceiling": ceiling,
     }
     if not args.no_makespan:
         res["makespan"] = makespans(torch, native, workloads, costmodel, args.makespan_reps,

@@ -311,6 +311,24 @@ int mandel_plan_autotune(const mandel_view *views, int32_t nviews, int32_t max_s
  * the rate of the wall clock that stamps mandel_sched.stats[4..6] (kHz). */
 int mandel_device_info(int32_t *compute_units, int32_t *wall_clock_khz);
 
+/*
+ * mandel_fp64_probe -- diagnostic: measures what the FP64 vector units deliver
+ * on this device, to put the render kernel's rate next to a measured ceiling.
+ *   kind 0: four independent fma chains per lane (peak FMA issue);
+ *   kind 1: the escape-time update alone (3 mul, sub, add, fma per iteration, no
+ *           test, no scheduling), one pixel per lane;
+ *   kind 2: the same update on two pixels per lane.
+ *   iters          iterations per lane, 1 .. 2^24 (8 updates or fmas each)
+ *   blocks_per_cu  256-thread workgroups per compute unit, 1 .. 8
+ *   sink           device double[compute units * blocks_per_cu * 256]: results
+ *                  written so the work cannot be optimised away
+ *   flops, ms      host: FP64 flops executed (fma = 2; the update counts its 7
+ *                  flops) and the kernel time of the second of two launches.
+ * Synchronous (waits for the kernel).
+ */
+int mandel_fp64_probe(int32_t kind, int32_t iters, int32_t blocks_per_cu, double *sink,
+                      double *flops, float *ms, void *stream);
+
 /* Text of the last error on this thread ("" if none). */
 const char *mandel_last_error(void);
 

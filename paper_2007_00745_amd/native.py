@@ -139,6 +139,9 @@ def lib() -> ctypes.CDLL:
         L.mandel_plan_autotune.restype = ctypes.c_int
         L.mandel_device_info.argtypes = [ctypes.POINTER(i32), ctypes.POINTER(i32)]
         L.mandel_device_info.restype = ctypes.c_int
+        L.mandel_fp64_probe.argtypes = [i32, i32, i32, P, ctypes.POINTER(d),
+                                        ctypes.POINTER(ctypes.c_float), P]
+        L.mandel_fp64_probe.restype = ctypes.c_int
         _lib = L
         return L
 
@@ -337,3 +340,16 @@ def device_info() -> dict:
     cus, khz = ctypes.c_int32(), ctypes.c_int32()
     check(lib().mandel_device_info(ctypes.byref(cus), ctypes.byref(khz)))
     return {"compute_units": int(cus.value), "wall_clock_khz": int(khz.value)}
+
+
+def fp64_probe(kind: int, iters: int = 4000, blocks_per_cu: int = 8, stream=None) -> dict:
+    """mandel_fp64_probe: kind 0 fma chains, 1 the bare update, 2 the update on two
+    pixels per lane.  Returns flops, milliseconds and TFLOP/s."""
+    import torch
+    info = device_info()
+    sink = torch.empty(info["compute_units"] * blocks_per_cu * 256, dtype=torch.float64,
+                       device="cuda")
+    fl, ms = ctypes.c_double(), ctypes.c_float()
+    check(lib().mandel_fp64_probe(kind, iters, blocks_per_cu, _ptr(sink), ctypes.byref(fl),
+                                  ctypes.byref(ms), _stream(stream)))
+    return {"flops": fl.value, "ms": ms.value, "tflops": fl.value / (ms.value / 1e3) / 1e12}

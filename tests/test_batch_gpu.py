@@ -244,3 +244,9 @@ def test_order_desc():
         assert np.all(np.diff(b) >= 0)
         if n > 10:
             assert np.all(np.isnan(kk[-5:]))
+
+
+def test_fp64_probe_runs():
+    for kind in (0, 1, 2):
+        r = native.fp64_probe(kind, iters=200, blocks_per_cu=2)
+        assert r["ms"] > 0 and r["flops"] > 0 and r["tflops"] < 200

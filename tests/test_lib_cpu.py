@@ -71,3 +71,14 @@ def test_empty_image_is_a_no_op():
 def test_invalid_schedules(s):
     sched = native.make_sched(**s)
     assert _call(sched=sched) == native.EINVAL
+
+
+def test_fp64_probe_argument_checks():
+    L = native.lib()
+    fl, ms = ctypes.c_double(), ctypes.c_float()
+    for kind, iters, bpc in ((3, 10, 1), (-1, 10, 1), (0, 0, 1), (0, (1 << 24) + 1, 1), (1, 10, 0),
+                             (2, 10, 9)):
+        assert L.mandel_fp64_probe(kind, iters, bpc, 0x1000, ctypes.byref(fl), ctypes.byref(ms),
+                                   None) == native.EINVAL
+    assert L.mandel_fp64_probe(0, 10, 1, None, ctypes.byref(fl), ctypes.byref(ms),
+                               None) == native.EINVAL
