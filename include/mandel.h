@@ -95,8 +95,8 @@ typedef struct mandel_sched {
     int32_t waves_per_group; /* wavefronts per workgroup, 1..16 [4] */
     int32_t check_every;     /* 1 = test |z|^2 > R^2 after every update only;
                                 0 = also allow deferred blocks of tests [0] */
-    int32_t block_iters;     /* longest deferred-test block K, 1..1024 [256] */
-    int32_t young_iters;     /* pixels younger than this are tested every update [8] */
+    int32_t block_iters;     /* longest deferred-test block K, 1..65536 [1024] */
+    int32_t young_iters;     /* pixels younger than this are tested every update [4] */
     int32_t refill_lanes;    /* while updates are tested one by one, lanes whose pixel
                                 finished are refilled once this many are idle, 1..64 [16] */
     const int32_t *order;    /* device int32[ntiles], ORDERED_TILES only: a permutation */
@@ -156,8 +156,8 @@ typedef struct mandel_tuning {
     int32_t tile_w, tile_h;  /* [64, 8] */
     int32_t grain;           /* tiles per queue claim [1] */
     int32_t waves_per_group; /* [4] */
-    int32_t block_iters;     /* [256] */
-    int32_t young_iters;     /* [8] */
+    int32_t block_iters;     /* [1024] */
+    int32_t young_iters;     /* [4] */
     int32_t groups;          /* persistent workgroups [fill the device] */
     int32_t refill_lanes;    /* [16], as in mandel_sched */
     int32_t tile_parts;      /* [1], as in mandel_sched */

@@ -185,11 +185,11 @@ int check_sched(const mandel_sched *s, mandel_sched *o)
     if (d.check_every != 0 && d.check_every != 1)
         return fail(MANDEL_EINVAL, "check_every must be 0 or 1");
     if (d.block_iters == 0)
-        d.block_iters = 256;
-    if (d.block_iters < 1 || d.block_iters > 1024)
-        return fail(MANDEL_EINVAL, "block_iters=%d outside [1, 1024]", d.block_iters);
+        d.block_iters = 1024;
+    if (d.block_iters < 1 || d.block_iters > 65536)
+        return fail(MANDEL_EINVAL, "block_iters=%d outside [1, 65536]", d.block_iters);
     if (d.young_iters == 0)
-        d.young_iters = 8;
+        d.young_iters = 4;
     if (d.young_iters < 0)
         return fail(MANDEL_EINVAL, "negative young_iters");
     if (d.refill_lanes == 0)

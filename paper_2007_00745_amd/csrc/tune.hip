@@ -75,8 +75,8 @@ extern "C" int mandel_plan_autotune(const mandel_view *views, int32_t nviews, in
     best->tile_h = 8;
     best->grain = 1;
     best->waves_per_group = 4;
-    best->block_iters = 256;
-    best->young_iters = 8;
+    best->block_iters = 1024;
+    best->young_iters = 4;
     best->refill_lanes = 16;
     best->tile_parts = 1;
     if (work.empty())
@@ -147,8 +147,8 @@ extern "C" int mandel_plan_autotune(const mandel_view *views, int32_t nviews, in
         t.tile_h = c.th;
         t.grain = c.grain;
         t.waves_per_group = c.wpg;
-        t.block_iters = 256;
-        t.young_iters = 8;
+        t.block_iters = 1024;
+        t.young_iters = 4;
         t.refill_lanes = 16;
         t.tile_parts = c.parts;
         mandel_plan *p = nullptr;

@@ -208,6 +208,36 @@ def test_nondefault_stream(c1_ref):
     assert np.array_equal(out.cpu().numpy(), c1_ref)
 
 
+def test_concurrent_streams(c1_ref):
+    # each (device, stream) has its own queue head, so calls on different streams may
+    # overlap; two plans (each with its own head) may overlap too
+    v = workloads.c1()
+    zoom = workloads.c3_scaled(745, 64, scale=16)[5]
+    want_zoom = ref(zoom)
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    outs = []
+    for rep in range(3):
+        with torch.cuda.stream(s1):
+            a = native.render(v.window, v.m, v.n, v.max_iter, v.R, stream=s1)
+        with torch.cuda.stream(s2):
+            b = native.render(zoom.window, zoom.m, zoom.n, zoom.max_iter, zoom.R, stream=s2)
+        outs.append((a, b))
+    torch.cuda.synchronize()
+    for a, b in outs:
+        assert np.array_equal(a.cpu().numpy(), c1_ref)
+        assert np.array_equal(b.cpu().numpy(), want_zoom)
+    p1, p2 = native.Plan([v]), native.Plan([zoom])
+    o1 = torch.empty(p1.out_size(), dtype=torch.int32, device="cuda")
+    o2 = torch.empty(p2.out_size(), dtype=torch.int32, device="cuda")
+    p1.launch(o1, stream=s1, use_graph=True)
+    p2.launch(o2, stream=s2, use_graph=True)
+    torch.cuda.synchronize()
+    assert np.array_equal(o1.view(v.m, v.n).cpu().numpy(), c1_ref)
+    assert np.array_equal(o2.view(zoom.m, zoom.n).cpu().numpy(), want_zoom)
+    p1.close()
+    p2.close()
+
+
 def test_c2_full_size_sampled():
     # The 8192 x 8192, max_iter 10000 view in the default launch: sampled pixels
     # (three whole rows, tile corners and 6000 random pixels) against the oracle,
