@@ -121,6 +121,12 @@ typedef struct mandel_sched {
                                 tile), so one expensive tile can be shared by several
                                 wavefronts; 1..64 [1]; GRID ignores it */
     int32_t reserved;
+    int64_t first_slot;      /* FCFS / ORDERED: the queue starts at this slot (slot
+                                q renders row part q mod tile_parts of tile q div
+                                tile_parts, through `order` for ORDERED); earlier
+                                slots are skipped and their pixels left untouched,
+                                so a launch can resume after slot k or cover only
+                                part of the queue; >= 0 [0]; must be 0 otherwise */
 } mandel_sched;
 
 /*
@@ -205,6 +211,8 @@ typedef struct mandel_launch {
                                 features (see mandel_plan_features) [128]; a model
                                 must be used with the cap it was trained with */
     int32_t reserved;
+    int64_t first_slot;      /* the render queue starts at this slot, as in
+                                mandel_sched [0] */
 } mandel_launch;
 
 /*

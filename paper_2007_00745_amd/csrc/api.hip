@@ -202,6 +202,10 @@ int check_sched(const mandel_sched *s, mandel_sched *o)
         return fail(MANDEL_EINVAL, "tile_parts=%d outside [1, 64]", d.tile_parts);
     if (d.policy == MANDEL_GRID_TILES)
         d.tile_parts = 1;
+    if (d.first_slot < 0)
+        return fail(MANDEL_EINVAL, "negative first_slot");
+    if (d.first_slot != 0 && d.policy != MANDEL_FCFS_TILES && d.policy != MANDEL_ORDERED_TILES)
+        return fail(MANDEL_EINVAL, "first_slot applies to the queue policies only");
     if (d.policy == MANDEL_ORDERED_TILES && !d.order)
         return fail(MANDEL_EINVAL, "ORDERED_TILES needs an order array");
     *o = d;
@@ -308,6 +312,7 @@ int mandel_render_sched(const mandel_window *w, int32_t m, int32_t n, int32_t ma
     a.young_iters = s.young_iters;
     a.refill_lanes = s.refill_lanes;
     a.parts = s.tile_parts;
+    a.first_slot = s.first_slot;
     a.out = out;
     a.order = s.order;
     a.tile_cost = rows ? nullptr : s.tile_cost;
@@ -329,7 +334,8 @@ int mandel_render_sched(const mandel_window *w, int32_t m, int32_t n, int32_t ma
         if (rc)
             return rc;
     }
-    hipError_t e = launch_clear(head, a.tile_cost, a.claims, a.tile_cost || a.claims ? ntiles : 0, a.stats, st);
+    hipError_t e = launch_clear(head, s.first_slot, a.tile_cost, a.claims,
+                                a.tile_cost || a.claims ? ntiles : 0, a.stats, st);
     if (e != hipSuccess)
         return hip_fail(e, "clear launch");
     e = launch_render(a, s.policy, false, s.check_every == 0, grid, block, st);

@@ -25,6 +25,7 @@ struct GraphEntry {
     int64_t *tile_cost;
     uint64_t *stats;
     int32_t probe_cap;
+    int64_t first_slot;
     hipGraph_t graph;
     hipGraphExec_t exec;
 };
@@ -153,6 +154,7 @@ int enqueue(mandel_plan *p, int32_t *out, const mandel_launch &la, hipStream_t s
     a.young_iters = p->tune.young_iters;
     a.refill_lanes = p->tune.refill_lanes;
     a.parts = p->tune.tile_parts;
+    a.first_slot = la.first_slot;
     a.out = out;
     a.head = p->d_head;
     a.order = order;
@@ -169,7 +171,8 @@ int enqueue(mandel_plan *p, int32_t *out, const mandel_launch &la, hipStream_t s
     int rc = tile_grid(sc, true, p->ntiles, &grid, &block);
     if (rc)
         return rc;
-    e = launch_clear(p->d_head, la.tile_cost, nullptr, la.tile_cost ? p->ntiles : 0, la.stats, s);
+    e = launch_clear(p->d_head, la.first_slot, la.tile_cost, nullptr,
+                     la.tile_cost ? p->ntiles : 0, la.stats, s);
     if (e != hipSuccess)
         return hip_fail(e, "clear launch");
     e = launch_render(a, policy, true, true, grid, block, s);
@@ -274,6 +277,8 @@ int mandel_plan_launch(mandel_plan *p, int32_t *out, const mandel_launch *args, 
         la.probe_cap = 128;
     if (la.probe_cap < 1 || la.probe_cap > (1 << 20))
         return fail(MANDEL_EINVAL, "probe_cap=%d outside [1, 2^20]", la.probe_cap);
+    if (la.first_slot < 0)
+        return fail(MANDEL_EINVAL, "negative first_slot");
     if (p->ntiles == 0)
         return MANDEL_OK;
     if (!out)
@@ -289,7 +294,8 @@ int mandel_plan_launch(mandel_plan *p, int32_t *out, const mandel_launch *args, 
 
     for (const GraphEntry &g : p->graphs) {
         if (g.out == out && g.mode == la.mode && g.order == la.order && g.mlp == la.mlp &&
-            g.tile_cost == la.tile_cost && g.stats == la.stats && g.probe_cap == la.probe_cap) {
+            g.tile_cost == la.tile_cost && g.stats == la.stats && g.probe_cap == la.probe_cap &&
+            g.first_slot == la.first_slot) {
             hipError_t e = hipGraphLaunch(g.exec, s);
             return e == hipSuccess ? MANDEL_OK : hip_fail(e, "hipGraphLaunch");
         }
@@ -302,6 +308,7 @@ int mandel_plan_launch(mandel_plan *p, int32_t *out, const mandel_launch *args, 
     g.tile_cost = la.tile_cost;
     g.stats = la.stats;
     g.probe_cap = la.probe_cap;
+    g.first_slot = la.first_slot;
     g.graph = nullptr;
     g.exec = nullptr;
     hipError_t e = hipStreamBeginCapture(p->capture, hipStreamCaptureModeThreadLocal);

@@ -38,6 +38,7 @@ struct RenderArgs {
     int32_t young_iters;           // P: pixels younger than P updates are tested every update
     int32_t refill_lanes;          // checked mode refills once this many lanes are idle
     int32_t parts;                 // queue items per tile (row parts), >= 1; 1 for GRID
+    int64_t first_slot;            // FCFS / ORDERED: the queue starts at this slot
     int32_t *out;                  // output base
     unsigned long long *head;      // queue head (FCFS / ORDERED)
     const int32_t *order;          // ORDERED: queue slot -> tile id
@@ -48,8 +49,8 @@ struct RenderArgs {
 
 hipError_t launch_render(const RenderArgs &a, int policy, bool batch, bool defer, dim3 grid,
                          dim3 block, hipStream_t s);
-hipError_t launch_clear(unsigned long long *head, int64_t *tile_cost, int32_t *claims,
-                        int64_t ntiles, uint64_t *stats, hipStream_t s);
+hipError_t launch_clear(unsigned long long *head, int64_t first_slot, int64_t *tile_cost,
+                        int32_t *claims, int64_t ntiles, uint64_t *stats, hipStream_t s);
 int persistent_blocks_per_cu(int policy, bool batch, bool defer, int threads);
 
 } // namespace mandel

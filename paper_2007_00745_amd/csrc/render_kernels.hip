@@ -8,14 +8,16 @@
 //     source chosen by the policy -- a device-wide atomic queue (the analogue
 //     of Sec. III-B), a permuted queue, the contiguous row blocks of Sec. III-A
 //     or the alternating rows of Sec. III-C;
-//   * a lane that finishes its pixel takes the next pixel of the wave's
-//     current item at once (ballot + mbcnt compaction), and the wave claims
-//     the next item as soon as the current one has no pixels left, so lanes
-//     idle only in the very last item of the whole launch;
+//   * lanes whose pixel finished take the next pixels of the wave's current
+//     item (ballot + mbcnt compaction), and the wave claims the next item as
+//     soon as the current one has no pixels left, so lanes idle only briefly
+//     (until a refill round) and in the last items of the whole launch;
 //   * the |z|^2 > R^2 test may be deferred over blocks of K updates for
-//     pixels where an escape provably cannot be undone (see safe2 below);
-//     a lane found escaped at the end of a block rewinds to its snapshot and
-//     replays the block with a test after every update, so the count is exact.
+//     pixels where an escape provably cannot be undone (R >= 2 and
+//     |c| <= (R^2 - R)(1 - 2^-20): after the first escape |z| keeps growing,
+//     and inf/NaN never become finite again); a lane found escaped at the end
+//     of a block rewinds to its snapshot and replays the block with a test
+//     after every update, so the count is exact.
 //
 // Arithmetic contract (must match the CPU definition bit for bit): IEEE
 // binary64, round to nearest even, one rounding per operation, in the order
@@ -105,13 +107,13 @@ __device__ __forceinline__ int32_t find_view(const ViewDesc *views, int32_t nvie
 } // namespace
 
 // Clears the queue head and the optional per-tile logs before a launch.
-__global__ void clear_kernel(unsigned long long *head, int64_t *tile_cost, int32_t *claims,
-                             int64_t ntiles, uint64_t *stats)
+__global__ void clear_kernel(unsigned long long *head, int64_t first_slot, int64_t *tile_cost,
+                             int32_t *claims, int64_t ntiles, uint64_t *stats)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
     if (i == 0 && head)
-        *head = 0ull;
+        *head = (unsigned long long)first_slot;
     if (i == 0 && stats) {
         // per-launch timestamps (wall clock ticks): first claim, queue dry, last exit
         stats[4] = ~0ull;
@@ -172,7 +174,7 @@ __global__ void __launch_bounds__(1024) render_kernel(RenderArgs a)
                             q = atomicAdd(a.head, (unsigned long long)a.grain);
                         int64_t qb = bcast_i64((int64_t)q);
                         if (a.stats && lane == 0) {
-                            if (qb == 0)
+                            if (qb == a.first_slot)
                                 atomicMin((unsigned long long *)&a.stats[4],
                                           (unsigned long long)wall_clock64());
                             if (qb >= nslots && qb < nslots + a.grain)
@@ -572,16 +574,16 @@ hipError_t launch_render(const RenderArgs &a, int policy, bool batch, bool defer
     }
 }
 
-hipError_t launch_clear(unsigned long long *head, int64_t *tile_cost, int32_t *claims,
-                        int64_t ntiles, uint64_t *stats, hipStream_t s)
+hipError_t launch_clear(unsigned long long *head, int64_t first_slot, int64_t *tile_cost,
+                        int32_t *claims, int64_t ntiles, uint64_t *stats, hipStream_t s)
 {
     int64_t blocks = (ntiles + 255) / 256;
     if (blocks < 1)
         blocks = 1;
     if (blocks > 4096)
         blocks = 4096;
-    hipLaunchKernelGGL(clear_kernel, dim3((unsigned)blocks), dim3(256), 0, s, head, tile_cost,
-                       claims, ntiles, stats);
+    hipLaunchKernelGGL(clear_kernel, dim3((unsigned)blocks), dim3(256), 0, s, head, first_slot,
+                       tile_cost, claims, ntiles, stats);
     return hipGetLastError();
 }
 

@@ -208,6 +208,34 @@ def test_nondefault_stream(c1_ref):
     assert np.array_equal(out.cpu().numpy(), c1_ref)
 
 
+def test_forced_queue_start(c1_ref):
+    # The queue may start at any slot k (resume after slot k): slots < k are skipped and
+    # their pixels keep the sentinel, every later slot is rendered exactly; k >= the
+    # number of slots renders nothing.
+    v = workloads.c1()
+    tw, th = 64, 8
+    nt = native.tile_count(v.m, v.n, tw, th)
+    tx = -(-v.n // tw)
+    rng = np.random.default_rng(4)
+    for policy, parts, k in (("fcfs", 1, 0), ("fcfs", 1, 137), ("fcfs", 1, nt), ("fcfs", 4, 251),
+                             ("ordered", 1, 300), ("ordered", 2, 777), ("fcfs", 1, nt + 99)):
+        order = torch.tensor(rng.permutation(nt), dtype=torch.int32, device="cuda")
+        out = torch.full((v.m, v.n), -1, dtype=torch.int32, device="cuda")
+        kw = dict(order=order) if policy == "ordered" else {}
+        native.render_sched(v.window, v.m, v.n, v.max_iter, v.R, out=out, policy=policy,
+                            tile_parts=parts, first_slot=k, **kw)
+        torch.cuda.synchronize()
+        got = out.cpu().numpy()
+        tiles = order.cpu().numpy() if policy == "ordered" else np.arange(nt)
+        want = np.full_like(c1_ref, -1)
+        for q in range(k, nt * parts):
+            t, p = tiles[q // parts], q % parts
+            y0, x0 = (t // tx) * th, (t % tx) * tw
+            r0, r1 = y0 + (p * th) // parts, y0 + ((p + 1) * th) // parts
+            want[r0:r1, x0:x0 + tw] = c1_ref[r0:r1, x0:x0 + tw]
+        assert np.array_equal(got, want), (policy, parts, k)
+
+
 def test_concurrent_streams(c1_ref):
     # each (device, stream) has its own queue head, so calls on different streams may
     # overlap; two plans (each with its own head) may overlap too

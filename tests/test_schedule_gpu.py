@@ -121,3 +121,46 @@ def test_stress_batch_c5():
     assert np.array_equal(got, want)
     _sample_check(plan, out, rng, per_view=512, max_views=16)
     plan.close()
+
+
+@pytest.fixture(scope="module")
+def quick_model():
+    views = workloads.training_views(range(1000, 1004), per_seed=8, lo=128, hi=1024)
+    views += [workloads.c2(512, 2000)]
+    feat, target, _, tplan = costmodel.collect(views)
+    params, _ = costmodel.train(feat, target, epochs=4, seed=1)
+    tplan.close()
+    return params
+
+
+def test_bench_configuration_8192(quick_model):
+    # The launch the benchmark times, at full size: one-view plan of the 8192 x 8192 view,
+    # learned order, hipGraph replay.  Sampled pixels against the oracle; symmetry of
+    # the whole image; equality with the plain FCFS entry point.
+    v = workloads.c2()
+    plan = native.Plan([v])
+    out = torch.full((plan.out_size(),), -1, dtype=torch.int32, device="cuda")
+    for rep in range(2):
+        plan.launch(out, mode="learned", mlp=quick_model, use_graph=True)
+    torch.cuda.synchronize()
+    img = out.view(v.m, v.n)
+    assert torch.equal(img, img.flip(0))
+    plain = native.render(v.window, v.m, v.n, v.max_iter, v.R)
+    torch.cuda.synchronize()
+    assert torch.equal(plain, img)
+    _sample_check(plan, out, np.random.default_rng(8192), per_view=3000)
+    plan.close()
+
+
+def test_bench_configuration_batch(quick_model):
+    # The batched learned launch of the benchmark's makespan comparison, at full size
+    # (the 64-view batch, autotuned plan); sampled pixels of every view.
+    views = workloads.c3()
+    tun, _ = native.autotune(views)
+    plan = native.Plan(views, tun)
+    out = torch.full((plan.out_size(),), -1, dtype=torch.int32, device="cuda")
+    plan.launch(out, mode="learned", mlp=quick_model, use_graph=True)
+    torch.cuda.synchronize()
+    assert int(out.min().item()) >= 1
+    _sample_check(plan, out, np.random.default_rng(745), per_view=48)
+    plan.close()
