@@ -125,7 +125,7 @@ def train_cost_model(torch, native, workloads, costmodel):
 
 
 def makespans(torch, native, workloads, costmodel, reps: int, clock_khz: float,
-              params) -> dict:
+              params, cus: int) -> dict:
     """Uneven 64-view batch: per-view row partitions and FCFS vs one batched launch."""
     res = {}
     views = workloads.c3()
@@ -164,6 +164,28 @@ def makespans(torch, native, workloads, costmodel, reps: int, clock_khz: float,
     assert torch.equal(out, ref), "row partitions changed the counts"
     ms["fcfs_per_view"] = {"ms": timed_ms(torch, lambda: per_view("fcfs", None), 1, "fcfs/view")}
 
+    # The stricter static baseline: one launch in which the rows of all 64 views,
+    # concatenated, are split over W workgroups by the paper's partitions.  W = 7 per CU
+    # is every worker resident at once (4 wavefronts each); more workers than that wait
+    # for free slots and measured several times slower, so the sweep stops there.
+    for pol in ("static", "alternating"):
+        per_w = {}
+        for mult in (1, 2, 4, 7):
+            W = cus * mult
+            out.fill_(-1)
+            per_w[W] = timed_ms(torch, lambda: plan.launch(out, mode=pol, workers=W,
+                                                           use_graph=True), 1,
+                                f"concatenated {pol} W={W}")
+            assert torch.equal(out, ref), f"concatenated {pol} changed the counts"
+        W = min(per_w, key=per_w.get)
+        stats.zero_()
+        plan.launch(out, mode=pol, workers=W, stats=stats)
+        torch.cuda.synchronize()
+        st = [int(v) for v in stats.cpu().tolist()]
+        ms[f"{pol}_rows_concatenated"] = {"ms": per_w[W], "workers": W,
+                                          "ms_by_workers": per_w,
+                                          "tail": tail_fraction(st, clock_khz)}
+
     res["cost_model_eval"] = costmodel.evaluate(params, plan.features(),
                                                 native.cost_targets(cost))
     true_perm = torch.argsort(cost, descending=True).to(torch.int32)
@@ -184,6 +206,9 @@ def makespans(torch, native, workloads, costmodel, reps: int, clock_khz: float,
     static = min(ms["static_rows_per_view"]["ms"], ms["alternating_rows_per_view"]["ms"])
     res["speedup_batched_learned_vs_static_rows"] = static / ms["batched_learned_lpt"]["ms"]
     res["speedup_batched_fcfs_vs_static_rows"] = static / ms["batched_fcfs"]["ms"]
+    concat = min(ms["static_rows_concatenated"]["ms"], ms["alternating_rows_concatenated"]["ms"])
+    res["speedup_batched_learned_vs_concatenated_rows"] = concat / ms["batched_learned_lpt"]["ms"]
+    res["speedup_batched_fcfs_vs_concatenated_rows"] = concat / ms["batched_fcfs"]["ms"]
     res["batched_fcfs_pixel_iterations_per_s"] = sum_counts / (ms["batched_fcfs"]["ms"] / 1e3)
     plan.close()
     return res
@@ -256,8 +281,8 @@ def secondary_kernels(torch, native, plan, params, sum_probe_iters, reps: int) -
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--side", type=int, default=8192)
     ap.add_argument("--max-iter", type=int, default=10000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -359,6 +384,11 @@ def main():
         best = max(ceiling["update_loop"]["tflops"],
                    ceiling["update_loop_2_pixels_per_lane"]["tflops"])
         ceiling["render_frac_of_update_loop"] = render_tflops / best
+        # independent FMA chains issue at most one FP64 FMA per lane per clock: their rate
+        # over the nominal peak bounds the clock under FP64 load from below, and the
+        # render's share of that rate is its fraction of the clock-adjusted peak
+        ceiling["fp64_clock_ghz_lower_bound"] = 2.4 * ceiling["fma_chain"]["tflops"] / FP64_PEAK_TFLOPS
+        ceiling["render_frac_of_clock_adjusted_peak"] = render_tflops / ceiling["fma_chain"]["tflops"]
         log(f"bench: fp64 ceilings fma {ceiling['fma_chain']['tflops']:.1f}, update loop "
             f"{best:.1f} TFLOP/s")
         comp = comparisons(torch, native, view, plan, out, cost, sum_counts, stream)
@@ -400,6 +430,7 @@ def main():
         "lane_occupancy": lane_occ,
         "tail": tail_fraction(st, clock_khz),
         "ms_min": min(ms),
+        "ms_median": sorted(ms)[len(ms) // 2],
         "wall_s": wall,
         "device": dinfo,
         "roofline": {"bound": "alu", "achieved": render_tflops, "peak": FP64_PEAK_TFLOPS,
@@ -416,7 +447,7 @@ def main():
     }
     if not args.no_makespan:
         res["makespan"] = makespans(torch, native, workloads, costmodel, args.makespan_reps,
-                                    clock_khz, params)
+                                    clock_khz, params, int(dinfo["compute_units"]))
     if not args.no_cpu_baseline:
         threads = min(16, os.cpu_count() or 1)
         log(f"bench: cpu baseline on {threads} threads")

@@ -114,8 +114,10 @@ typedef struct mandel_sched {
                                 [1] sum of counts, [2] wavefronts that ran, [3] work
                                 items taken.  [4..6] are set per call, in wall-clock
                                 ticks (hipDeviceAttributeWallClockRate): [4] first
-                                queue claim, [5] first claim that found the queue
-                                empty, [6] last wavefront exit (tile policies) */
+                                queue claim (row policies: first row taken), [5]
+                                first claim that found the queue empty (row
+                                policies: first worker to run out of rows), [6]
+                                last wavefront exit; GRID sets only [6] */
     int32_t tile_parts;      /* FCFS / ORDERED: each tile is queued as this many row
                                 parts (rows [p*h/parts, (p+1)*h/parts) of an h-row
                                 tile), so one expensive tile can be shared by several
@@ -194,8 +196,16 @@ enum mandel_plan_mode {
     MANDEL_PLAN_ORDERED = 1,     /* queue over the caller's permutation `order` */
     MANDEL_PLAN_PROBE_LPT = 2,   /* probe features -> key = mean probe cost ->
                                     descending order -> ordered render */
-    MANDEL_PLAN_LEARNED_LPT = 3  /* probe features -> cost-model MLP -> descending
+    MANDEL_PLAN_LEARNED_LPT = 3, /* probe features -> cost-model MLP -> descending
                                     order -> ordered render */
+    /* The paper's row partitions applied to the whole batch as one image: the rows
+     * of all views are concatenated (view 0's rows, then view 1's, ...) and the
+     * M rows are split over W = `workers` workgroups as MANDEL_STATIC_ROWS
+     * (Sec. III-A) or MANDEL_ALTERNATING_ROWS (Sec. III-C) split one image's rows.
+     * No queue, order or cost model; tile_cost must be NULL and first_slot 0.
+     * Needs fewer than 2^31 rows in the plan. */
+    MANDEL_PLAN_STATIC_ROWS = 4,
+    MANDEL_PLAN_ALTERNATING_ROWS = 5
 };
 
 typedef struct mandel_launch {
@@ -210,9 +220,11 @@ typedef struct mandel_launch {
     int32_t probe_cap;       /* PROBE_LPT / LEARNED_LPT: probe iteration cap of the
                                 features (see mandel_plan_features) [128]; a model
                                 must be used with the cap it was trained with */
-    int32_t reserved;
-    int64_t first_slot;      /* the render queue starts at this slot, as in
-                                mandel_sched [0] */
+    int32_t workers;         /* STATIC_ROWS / ALTERNATING_ROWS: W workgroups of the
+                                plan's waves_per_group wavefronts (required >= 1);
+                                must be 0 in the other modes */
+    int64_t first_slot;      /* queue modes: the render queue starts at this slot, as
+                                in mandel_sched [0] */
 } mandel_launch;
 
 /*

@@ -25,6 +25,7 @@ struct GraphEntry {
     int64_t *tile_cost;
     uint64_t *stats;
     int32_t probe_cap;
+    int32_t workers;
     int64_t first_slot;
     hipGraph_t graph;
     hipGraphExec_t exec;
@@ -38,6 +39,7 @@ struct mandel_plan {
     mandel_tuning tune{};
     int64_t ntiles = 0;
     int64_t npixels = 0;
+    int64_t nrows = 0;
     ViewDesc *d_views = nullptr;
     unsigned long long *d_head = nullptr;
     // buffers of the ordered modes (allocated on first use)
@@ -139,7 +141,12 @@ int enqueue(mandel_plan *p, int32_t *out, const mandel_launch &la, hipStream_t s
             return hip_fail(e, "order launch");
         order = p->d_perm;
         policy = POLICY_ORDERED_TILES;
+    } else if (la.mode == MANDEL_PLAN_STATIC_ROWS) {
+        policy = POLICY_STATIC_ROWS;
+    } else if (la.mode == MANDEL_PLAN_ALTERNATING_ROWS) {
+        policy = POLICY_ALTERNATING_ROWS;
     }
+    const bool rows = policy == POLICY_STATIC_ROWS || policy == POLICY_ALTERNATING_ROWS;
 
     RenderArgs a;
     std::memset(&a, 0, sizeof a);
@@ -155,8 +162,9 @@ int enqueue(mandel_plan *p, int32_t *out, const mandel_launch &la, hipStream_t s
     a.refill_lanes = p->tune.refill_lanes;
     a.parts = p->tune.tile_parts;
     a.first_slot = la.first_slot;
+    a.nrows = p->nrows;
     a.out = out;
-    a.head = p->d_head;
+    a.head = rows ? nullptr : p->d_head;
     a.order = order;
     a.tile_cost = la.tile_cost;
     a.claims = nullptr;
@@ -166,12 +174,12 @@ int enqueue(mandel_plan *p, int32_t *out, const mandel_launch &la, hipStream_t s
     std::memset(&sc, 0, sizeof sc);
     sc.policy = policy;
     sc.waves_per_group = p->tune.waves_per_group;
-    sc.workers = p->tune.groups;
+    sc.workers = rows ? la.workers : p->tune.groups;
     dim3 grid, block;
     int rc = tile_grid(sc, true, p->ntiles, &grid, &block);
     if (rc)
         return rc;
-    e = launch_clear(p->d_head, la.first_slot, la.tile_cost, nullptr,
+    e = launch_clear(rows ? nullptr : p->d_head, la.first_slot, la.tile_cost, nullptr,
                      la.tile_cost ? p->ntiles : 0, la.stats, s);
     if (e != hipSuccess)
         return hip_fail(e, "clear launch");
@@ -217,7 +225,9 @@ int mandel_plan_create(const mandel_view *views, int32_t nviews, const mandel_tu
         }
         p->views[k].out_off = v.out_offset;
         p->views[k].tile_off = toff;
+        p->views[k].row_off = p->nrows;
         toff += tile_count(v.m, v.n, tu.tile_w, tu.tile_h);
+        p->nrows += v.m;
         npx += (int64_t)v.m * v.n;
     }
     if (toff >= ((int64_t)1 << 31)) {
@@ -267,8 +277,22 @@ int mandel_plan_launch(mandel_plan *p, int32_t *out, const mandel_launch *args, 
     std::memset(&la, 0, sizeof la);
     if (args)
         la = *args;
-    if (la.mode < MANDEL_PLAN_FCFS || la.mode > MANDEL_PLAN_LEARNED_LPT)
+    if (la.mode < MANDEL_PLAN_FCFS || la.mode > MANDEL_PLAN_ALTERNATING_ROWS)
         return fail(MANDEL_EINVAL, "unknown plan mode %d", la.mode);
+    const bool rows = la.mode == MANDEL_PLAN_STATIC_ROWS || la.mode == MANDEL_PLAN_ALTERNATING_ROWS;
+    if (rows) {
+        if (la.workers < 1)
+            return fail(MANDEL_EINVAL, "row modes need workers >= 1");
+        if (la.tile_cost)
+            return fail(MANDEL_EINVAL, "row modes log no tile costs (tile_cost must be NULL)");
+        if (la.first_slot != 0)
+            return fail(MANDEL_EINVAL, "row modes have no queue (first_slot must be 0)");
+        if (p->nrows >= ((int64_t)1 << 31))
+            return fail(MANDEL_EINVAL, "row modes need fewer than 2^31 rows (plan has %lld)",
+                        (long long)p->nrows);
+    } else if (la.workers != 0) {
+        return fail(MANDEL_EINVAL, "workers applies to the row modes only");
+    }
     if (la.mode == MANDEL_PLAN_ORDERED && !la.order)
         return fail(MANDEL_EINVAL, "ORDERED needs an order array");
     if (la.mode == MANDEL_PLAN_LEARNED_LPT && !la.mlp)
@@ -295,7 +319,7 @@ int mandel_plan_launch(mandel_plan *p, int32_t *out, const mandel_launch *args, 
     for (const GraphEntry &g : p->graphs) {
         if (g.out == out && g.mode == la.mode && g.order == la.order && g.mlp == la.mlp &&
             g.tile_cost == la.tile_cost && g.stats == la.stats && g.probe_cap == la.probe_cap &&
-            g.first_slot == la.first_slot) {
+            g.workers == la.workers && g.first_slot == la.first_slot) {
             hipError_t e = hipGraphLaunch(g.exec, s);
             return e == hipSuccess ? MANDEL_OK : hip_fail(e, "hipGraphLaunch");
         }
@@ -308,6 +332,7 @@ int mandel_plan_launch(mandel_plan *p, int32_t *out, const mandel_launch *args, 
     g.tile_cost = la.tile_cost;
     g.stats = la.stats;
     g.probe_cap = la.probe_cap;
+    g.workers = la.workers;
     g.first_slot = la.first_slot;
     g.graph = nullptr;
     g.exec = nullptr;

@@ -24,7 +24,9 @@ struct ViewDesc {
     int32_t max_iter;
     int32_t tiles_x;         // tiles per tile-row
     int32_t tiles_y;
-    int32_t pad[3];
+    int32_t pad;
+    int64_t row_off;         // batch row policies: index of this view's first row in the
+                             // concatenation of all views' rows
 };
 static_assert(sizeof(ViewDesc) == 96, "ViewDesc layout");
 
@@ -39,6 +41,7 @@ struct RenderArgs {
     int32_t refill_lanes;          // checked mode refills once this many lanes are idle
     int32_t parts;                 // queue items per tile (row parts), >= 1; 1 for GRID
     int64_t first_slot;            // FCFS / ORDERED: the queue starts at this slot
+    int64_t nrows;                 // batch row policies: rows of all views together
     int32_t *out;                  // output base
     unsigned long long *head;      // queue head (FCFS / ORDERED)
     const int32_t *order;          // ORDERED: queue slot -> tile id

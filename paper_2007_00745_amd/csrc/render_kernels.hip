@@ -90,13 +90,16 @@ __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v)
     return v;
 }
 
-// Tile id -> view index in a batch: the views hold ascending first-tile ids.
+// Tile id (or, with ROWS, row index) -> view index in a batch: the last view whose
+// first tile (first row) is at or before t.  The offsets ascend; empty views share
+// the next view's offset and are never returned for an existing tile or row.
+template <bool ROWS = false>
 __device__ __forceinline__ int32_t find_view(const ViewDesc *views, int32_t nviews, int64_t t)
 {
     int32_t lo = 0, hi = nviews - 1;
     while (lo < hi) {
         int32_t mid = (lo + hi + 1) >> 1;
-        if (views[mid].tile_off <= t)
+        if ((ROWS ? views[mid].row_off : views[mid].tile_off) <= t)
             lo = mid;
         else
             hi = mid - 1;
@@ -241,39 +244,60 @@ __global__ void __launch_bounds__(1024) render_kernel(RenderArgs a)
                 return true;
             }
         } else {
-            // Row policies: a workgroup is one worker r of W = gridDim.x.
-            const int32_t m = a.v0.m;
-            const int32_t W = (int32_t)gridDim.x;
-            const int32_t r = (int32_t)blockIdx.x;
-            const int32_t q = m / W;
+            // Row policies: a workgroup is one worker r of W = gridDim.x.  In a batch the
+            // rows of all views form one sequence (view 0's rows, then view 1's, ...)
+            // that is partitioned as one image of nrows rows.
+            int64_t M;
+            if constexpr (BATCH)
+                M = a.nrows;
+            else
+                M = a.v0.m;
+            const int64_t W = (int64_t)gridDim.x;
+            const int64_t r = (int64_t)blockIdx.x;
+            const int64_t q = M / W;
             int32_t k = 0;
             if (lane == 0)
                 k = atomicAdd(&lds_next_row, 1);
             k = bcast_i32(k);
-            int32_t row;
+            int64_t row, cnt;
             if constexpr (POLICY == POLICY_STATIC_ROWS) {
-                // Sec. III-A: S_r = q*r, E_r = q*(r+1) - 1, last worker + (m mod W).
-                int32_t cnt = q + (r == W - 1 ? m % W : 0);
-                if (k >= cnt)
-                    return false;
+                // Sec. III-A: S_r = q*r, E_r = q*(r+1) - 1, last worker + (M mod W).
+                cnt = q + (r == W - 1 ? M % W : 0);
                 row = q * r + k;
             } else {
-                // Sec. III-C: rows r + k*W for k < q; worker 0 also does rows q*W .. m-1.
-                int32_t cnt = q + (r == 0 ? m - q * W : 0);
-                if (k >= cnt)
-                    return false;
-                row = k < q ? r + k * W : q * W + (k - q);
+                // Sec. III-C: rows r + k*W for k < q; worker 0 also does rows q*W .. M-1.
+                cnt = q + (r == 0 ? M - q * W : 0);
+                row = k < q ? r + (int64_t)k * W : q * W + (k - q);
             }
+            if (a.stats && lane == 0) {
+                if (k == 0 && cnt > 0)
+                    atomicMin((unsigned long long *)&a.stats[4],
+                              (unsigned long long)wall_clock64());
+                if (k == cnt)
+                    atomicMin((unsigned long long *)&a.stats[5],
+                              (unsigned long long)wall_clock64());
+            }
+            if (k >= cnt)
+                return false;
             if (a.claims && lane == 0)
-                atomicAdd(&a.claims[row], r + 1); // ownership log: worker r + 1 per take
-            s_view = 0;
+                atomicAdd(&a.claims[row], (int32_t)r + 1); // ownership log: worker r + 1 per take
+            int32_t v = 0, vrow, vn;
+            if constexpr (BATCH) {
+                v = bcast_i32(find_view<true>(a.views, a.nviews, row));
+                vrow = (int32_t)(row - a.views[v].row_off);
+                vn = a.views[v].n;
+            } else {
+                vrow = (int32_t)row;
+                vn = a.v0.n;
+            }
+            s_view = v;
             s_x0 = 0;
-            s_y0 = row;
-            s_w = a.v0.n;
+            s_y0 = vrow;
+            s_w = vn;
             s_next = 0;
             s_in = 0;
             s_jn = 0;
-            s_cnt = a.v0.n;
+            s_cnt = vn;
             s_tile = row;
             ++taken;
             return true;
@@ -554,6 +578,10 @@ hipError_t launch_render(const RenderArgs &a, int policy, bool batch, bool defer
             return launch_defer<POLICY_ORDERED_TILES, true>(a, defer, grid, block, s);
         case POLICY_GRID_TILES:
             return launch_defer<POLICY_GRID_TILES, true>(a, defer, grid, block, s);
+        case POLICY_STATIC_ROWS:
+            return launch_defer<POLICY_STATIC_ROWS, true>(a, defer, grid, block, s);
+        case POLICY_ALTERNATING_ROWS:
+            return launch_defer<POLICY_ALTERNATING_ROWS, true>(a, defer, grid, block, s);
         default:
             return hipErrorInvalidValue;
         }

@@ -69,11 +69,11 @@ class LaunchC(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("use_graph", ctypes.c_int32),
                 ("order", ctypes.c_void_p), ("mlp", ctypes.c_void_p),
                 ("tile_cost", ctypes.c_void_p), ("stats", ctypes.c_void_p),
-                ("probe_cap", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("probe_cap", ctypes.c_int32), ("workers", ctypes.c_int32),
                 ("first_slot", ctypes.c_int64)]
 
 
-PLAN_MODES = {"fcfs": 0, "ordered": 1, "probe": 2, "learned": 3}
+PLAN_MODES = {"fcfs": 0, "ordered": 1, "probe": 2, "learned": 3, "static": 4, "alternating": 5}
 NFEAT = 68
 MLP_PARAMS = 8777
 MLP_NORM = 136
@@ -260,10 +260,10 @@ class Plan:
         return max((o + v.m * v.n for o, v in zip(self.out_offsets, self.views)), default=0)
 
     def launch(self, out, mode="fcfs", use_graph=False, order=None, mlp=None, tile_cost=None,
-               stats=None, probe_cap=0, first_slot=0, stream=None):
+               stats=None, probe_cap=0, first_slot=0, workers=0, stream=None):
         la = LaunchC(PLAN_MODES[mode] if isinstance(mode, str) else int(mode), int(use_graph),
-                     _ptr(order), _ptr(mlp), _ptr(tile_cost), _ptr(stats), int(probe_cap), 0,
-                     int(first_slot))
+                     _ptr(order), _ptr(mlp), _ptr(tile_cost), _ptr(stats), int(probe_cap),
+                     int(workers), int(first_slot))
         check(lib().mandel_plan_launch(self._h, _ptr(out), ctypes.byref(la), _stream(stream)))
         return out
 

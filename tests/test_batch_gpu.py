@@ -91,6 +91,38 @@ def test_plan_modes_and_graph_replays(small_batch, parts):
     plan.close()
 
 
+@pytest.mark.parametrize("mode", ["static", "alternating"])
+def test_plan_row_modes(small_batch, mode):
+    # The paper's row partitions over the concatenated rows of the whole batch
+    # (Sec. III-A and III-C): every worker count gives the oracle's images, also
+    # with fewer rows than workers, a view of zero-width rows and graph replays.
+    views, want = small_batch
+    views = views + [workloads.View((0.1, 0.2, 0.01, 0.01), 5, 0, 40)]
+    want = want + [np.zeros((5, 0), dtype=np.int32)]
+    nrows = sum(v.m for v in views)
+    plan = native.Plan(views)
+    stats = torch.zeros(8, dtype=torch.int64, device="cuda")
+    for W in (1, 3, 7, 64, 1000, nrows, nrows + 5):
+        for use_graph in (False, True, True):
+            _log(f"rows {mode} W={W} graph={use_graph}")
+            out = torch.full((plan.out_size(),), -1, dtype=torch.int32, device="cuda")
+            stats.zero_()
+            plan.launch(out, mode=mode, workers=W, stats=stats, use_graph=use_graph)
+            torch.cuda.synchronize()
+            _check(plan, out, want)
+            st = stats.cpu().numpy()
+            assert st[3] == nrows and st[1] == sum(int(w.sum()) for w in want)
+            assert st[4] <= st[6] and st[5] <= st[6]
+    for bad in (dict(workers=0), dict(workers=-2), dict(workers=4, first_slot=1),
+                dict(workers=4, tile_cost=torch.zeros(plan.ntiles, dtype=torch.int64,
+                                                      device="cuda"))):
+        with pytest.raises(native.MandelError):
+            plan.launch(out, mode=mode, **bad)
+    with pytest.raises(native.MandelError):
+        plan.launch(out, mode="fcfs", workers=4)
+    plan.close()
+
+
 def _tile_sums(views, imgs, tw, th):
     sums = []
     for v, img in zip(views, imgs):
