@@ -90,12 +90,45 @@ __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v)
     return v;
 }
 
+// The view table and the queue order are never written by the render kernel, so they
+// are read as constant memory: wave-uniform reads then go through the scalar cache
+// into SGPRs instead of 64 per-lane vector loads.
+template <typename T>
+__device__ __forceinline__ const __attribute__((address_space(4))) T *as_const(const T *p)
+{
+    return (const __attribute__((address_space(4))) T *)p;
+}
+
+// Copy of a descriptor read from constant memory (fields the caller does not use are
+// never loaded).
+__device__ __forceinline__ ViewDesc load_view(const __attribute__((address_space(4))) ViewDesc *p)
+{
+    ViewDesc d;
+    d.cx0 = p->cx0;
+    d.cy0 = p->cy0;
+    d.dx = p->dx;
+    d.dy = p->dy;
+    d.R2 = p->R2;
+    d.safe2 = p->safe2;
+    d.out_off = p->out_off;
+    d.tile_off = p->tile_off;
+    d.m = p->m;
+    d.n = p->n;
+    d.max_iter = p->max_iter;
+    d.tiles_x = p->tiles_x;
+    d.tiles_y = p->tiles_y;
+    d.pad = p->pad;
+    d.row_off = p->row_off;
+    return d;
+}
+
 // Tile id (or, with ROWS, row index) -> view index in a batch: the last view whose
 // first tile (first row) is at or before t.  The offsets ascend; empty views share
 // the next view's offset and are never returned for an existing tile or row.
 template <bool ROWS = false>
-__device__ __forceinline__ int32_t find_view(const ViewDesc *views, int32_t nviews, int64_t t)
+__device__ __forceinline__ int32_t find_view(const ViewDesc *table, int32_t nviews, int64_t t)
 {
+    const auto *views = as_const(table);
     int32_t lo = 0, hi = nviews - 1;
     while (lo < hi) {
         int32_t mid = (lo + hi + 1) >> 1;
@@ -196,7 +229,7 @@ __global__ void __launch_bounds__(1024) render_kernel(RenderArgs a)
                     const int64_t item = a.parts == 1 ? slot : slot / a.parts;
                     part = (int32_t)(slot - item * a.parts);
                     if constexpr (POLICY == POLICY_ORDERED_TILES) {
-                        t = (int64_t)a.order[item];
+                        t = (int64_t)as_const(a.order)[item];
                         if (t < 0 || t >= a.ntiles)
                             continue; // not a tile id: skipped, never dereferenced
                     } else {
@@ -208,10 +241,11 @@ __global__ void __launch_bounds__(1024) render_kernel(RenderArgs a)
                 int32_t tiles_x, vm, vn;
                 if constexpr (BATCH) {
                     v = bcast_i32(find_view(a.views, a.nviews, t));
-                    tile_off = a.views[v].tile_off;
-                    tiles_x = a.views[v].tiles_x;
-                    vm = a.views[v].m;
-                    vn = a.views[v].n;
+                    const auto *vd = as_const(a.views) + v;
+                    tile_off = vd->tile_off;
+                    tiles_x = vd->tiles_x;
+                    vm = vd->m;
+                    vn = vd->n;
                 } else {
                     tile_off = a.v0.tile_off;
                     tiles_x = a.v0.tiles_x;
@@ -284,8 +318,9 @@ __global__ void __launch_bounds__(1024) render_kernel(RenderArgs a)
             int32_t v = 0, vrow, vn;
             if constexpr (BATCH) {
                 v = bcast_i32(find_view<true>(a.views, a.nviews, row));
-                vrow = (int32_t)(row - a.views[v].row_off);
-                vn = a.views[v].n;
+                const auto *vd = as_const(a.views) + v;
+                vrow = (int32_t)(row - vd->row_off);
+                vn = vd->n;
             } else {
                 vrow = (int32_t)row;
                 vn = a.v0.n;
@@ -332,7 +367,7 @@ __global__ void __launch_bounds__(1024) render_kernel(RenderArgs a)
             if (!active && (int32_t)rk < take) {
                 ViewDesc vv;
                 if constexpr (BATCH)
-                    vv = a.views[s_view];
+                    vv = load_view(as_const(a.views) + bcast_i32(s_view));
                 else
                     vv = a.v0;
                 const ViewDesc *vd = &vv;

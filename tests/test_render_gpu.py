@@ -138,13 +138,32 @@ def test_empty_views():
 
 @pytest.mark.parametrize("mi", [1, 2, 3, 17])
 def test_tiny_max_iter(mi):
-    v = workloads.View(workloads.c1().window, 48, 64, mi, 2.0)
     v = workloads.View(workloads.window_from_bounds(-2, 1, -1.2, 1.2, 48, 64), 48, 64, mi, 2.0)
     for ce in (0, 1):
         got = gpu_render(v, check_every=ce)
         assert np.array_equal(got, ref(v))
         if mi == 1:
             assert np.all(got == 1)
+
+
+def test_large_max_iter():
+    # Limits near the top of the range (2^26 .. 2^30): 1 x 1 views whose pixel centre is
+    # exactly c.  Bounded orbits (c = 0, the period-2 orbit of -1, the tie orbit of -2)
+    # run all 2^26 updates; the others escape early under max_iter 2^30 (the cusp point
+    # 1/4 + 1e-10 after about pi / sqrt(1e-10) updates), exercising the iteration budget
+    # and deadline arithmetic with max_iter - 1 close to 2^30.
+    pts = [(0.0, 0.0, 1 << 26), (-1.0, 0.0, 1 << 26), (-2.0, 0.0, 1 << 26),
+           (0.25 + 1e-10, 0.0, 1 << 30), (-0.75, 1e-5, 1 << 30), (2.0, 0.0, 1 << 30),
+           (0.4, 0.3, 1 << 30)]
+    views = [workloads.View((cx, cy, 1e-3, 1e-3), 1, 1, mi) for cx, cy, mi in pts]
+    want = [oracle.escape_count(cx, cy, mi, 2.0) for cx, cy, mi in pts]
+    assert want[:3] == [1 << 26] * 3 and want[5] == 2
+    assert abs(want[3] * 1e-5 - np.pi) < 1e-3
+    plan = native.Plan(views)
+    out = torch.full((plan.out_size(),), -1, dtype=torch.int32, device="cuda")
+    plan.launch(out)
+    torch.cuda.synchronize()
+    assert out.cpu().tolist() == want
 
 
 @pytest.mark.parametrize("R", [0.5, 1.0, 1.999, 2.0, 2.5, 400.0, 1e150])
