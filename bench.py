@@ -76,10 +76,44 @@ def cpu_baseline(view, rows_step: int, threads: int) -> dict:
                                   threads=threads)
     dt = time.perf_counter() - t0
     total = int(counts.sum(dtype=np.int64))
+    # one core on the small 640 x 480 view, whole image
+    from paper_2007_00745_amd import workloads
+    c1 = workloads.c1()
+    t1 = time.perf_counter()
+    img = oracle.render(c1.window, c1.m, c1.n, c1.max_iter, c1.R)
+    d1 = time.perf_counter() - t1
+    s1 = int(img.sum(dtype=np.int64))
     return {"value": total / dt, "unit": "pixel-iterations/s", "cores": threads,
             "kind": "oracle",
             "sample": f"rows i = 0 mod {rows_step} of the {view.m}x{view.n} view "
-                      f"({len(rows)} rows, {idx.size} px, {total} iterations, {dt:.2f} s wall)"}
+                      f"({len(rows)} rows, {idx.size} px, {total} iterations, {dt:.2f} s wall)",
+            "single_core": {"value": s1 / d1, "seconds": d1, "iterations": s1,
+                            "workload": f"{c1.m}x{c1.n} full view, max_iter {c1.max_iter}, "
+                                        "whole image, one thread"}}
+
+
+# Computation times of the paper's alternating-row run with 32 MPI tasks on two Xeon
+# Gold 6150 nodes, 8000 x 8000 image, iterationMax 2000, escape radius 400 (the five
+# runs of its appendix listing; the window is not stated).
+PAPER_ALT32_COMPUTE_S = (2.855784, 2.857663, 2.858120, 2.855122, 2.855696)
+
+
+def paper_context(torch, native, workloads) -> dict:
+    """The paper's image shape on this GPU, with the window assumed to be the
+    640 x 480 view's (re [-2, 1], im [-1.2, 1.2]): context, not a like-for-like figure."""
+    v = workloads.paper_view()
+    out = torch.empty((v.m, v.n), dtype=torch.int32, device="cuda")
+    ms = timed_ms(torch, lambda: native.render(v.window, v.m, v.n, v.max_iter, v.R, out=out),
+                  3, "paper-shaped view")
+    total = int(out.sum(dtype=torch.int64).item())
+    paper_s = sum(PAPER_ALT32_COMPUTE_S) / len(PAPER_ALT32_COMPUTE_S)
+    return {"workload": f"{v.m}x{v.n}, max_iter {v.max_iter}, R {v.R}, window assumed "
+                        "re[-2,1] x im[-1.2,1.2]",
+            "gpu_ms": ms, "sum_counts": total,
+            "gpu_pixel_iterations_per_s": total / (ms / 1e3),
+            "paper_alternating_32_tasks_compute_s": paper_s,
+            "paper_pixel_iterations_per_s_if_same_window": total / paper_s,
+            "time_ratio": paper_s / (ms / 1e3)}
 
 
 def timed_ms(torch, fn, reps: int, name: str) -> float:
@@ -445,6 +479,8 @@ def main():
         "secondary_kernels": kernels,
         "fp64_ceiling": ceiling,
     }
+    if not args.profile:
+        res["paper_context"] = paper_context(torch, native, workloads)
     if not args.no_makespan:
         res["makespan"] = makespans(torch, native, workloads, costmodel, args.makespan_reps,
                                     clock_khz, params, int(dinfo["compute_units"]))

@@ -117,12 +117,22 @@ typedef struct mandel_sched {
                                 queue claim (row policies: first row taken), [5]
                                 first claim that found the queue empty (row
                                 policies: first worker to run out of rows), [6]
-                                last wavefront exit; GRID sets only [6] */
+                                last wavefront exit; GRID sets only [6].  [7]
+                                accumulates the updates skipped by periodicity
+                                detection */
     int32_t tile_parts;      /* FCFS / ORDERED: each tile is queued as this many row
                                 parts (rows [p*h/parts, (p+1)*h/parts) of an h-row
                                 tile), so one expensive tile can be shared by several
                                 wavefronts; 1..64 [1]; GRID ignores it */
-    int32_t reserved;
+    int32_t periodicity;     /* 1: exact periodicity detection (needs check_every 0):
+                                in each deferred block the last 32 states of every
+                                lane are compared bit for bit with the block-start
+                                state; a lane whose state recurs (and did not escape)
+                                is on a cycle of non-escaping states and gets
+                                max_iter at once.  Every cycle of period <= 32 is
+                                found one block after the orbit reaches it.  Counts
+                                are unchanged; stats[7] adds the updates skipped.
+                                0: off [0] */
     int64_t first_slot;      /* FCFS / ORDERED: the queue starts at this slot (slot
                                 q renders row part q mod tile_parts of tile q div
                                 tile_parts, through `order` for ORDERED); earlier
@@ -225,6 +235,8 @@ typedef struct mandel_launch {
                                 must be 0 in the other modes */
     int64_t first_slot;      /* queue modes: the render queue starts at this slot, as
                                 in mandel_sched [0] */
+    int32_t periodicity;     /* 1: exact periodicity detection, as in mandel_sched [0] */
+    int32_t reserved;        /* must be 0 */
 } mandel_launch;
 
 /*

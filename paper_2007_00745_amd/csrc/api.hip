@@ -184,6 +184,10 @@ int check_sched(const mandel_sched *s, mandel_sched *o)
         return fail(MANDEL_EINVAL, "row policies need workers >= 1");
     if (d.check_every != 0 && d.check_every != 1)
         return fail(MANDEL_EINVAL, "check_every must be 0 or 1");
+    if (d.periodicity != 0 && d.periodicity != 1)
+        return fail(MANDEL_EINVAL, "periodicity must be 0 or 1");
+    if (d.periodicity && d.check_every)
+        return fail(MANDEL_EINVAL, "periodicity detection needs deferred tests (check_every 0)");
     if (d.block_iters == 0)
         d.block_iters = 1024;
     if (d.block_iters < 1 || d.block_iters > 65536)
@@ -212,6 +216,14 @@ int check_sched(const mandel_sched *s, mandel_sched *o)
     return MANDEL_OK;
 }
 
+// Escape-test schedule of a checked schedule.
+int test_mode(const mandel_sched &s)
+{
+    if (s.check_every)
+        return TESTS_EVERY_UPDATE;
+    return s.periodicity ? TESTS_DEFERRED_PERIODIC : TESTS_DEFERRED;
+}
+
 // Launch geometry for a tile policy: persistent groups or one group per tile.
 int tile_grid(const mandel_sched &s, bool batch, int64_t ntiles, dim3 *grid, dim3 *block)
 {
@@ -231,8 +243,7 @@ int tile_grid(const mandel_sched &s, bool batch, int64_t ntiles, dim3 *grid, dim
         int rc = device_cus(&cus);
         if (rc)
             return rc;
-        const bool defer = s.check_every == 0;
-        groups = cus * persistent_blocks_per_cu(s.policy, batch, defer, threads);
+        groups = cus * persistent_blocks_per_cu(s.policy, batch, test_mode(s), threads);
     }
     *grid = dim3((unsigned)groups);
     *block = dim3((unsigned)threads);
@@ -338,7 +349,7 @@ int mandel_render_sched(const mandel_window *w, int32_t m, int32_t n, int32_t ma
                                 a.tile_cost || a.claims ? ntiles : 0, a.stats, st);
     if (e != hipSuccess)
         return hip_fail(e, "clear launch");
-    e = launch_render(a, s.policy, false, s.check_every == 0, grid, block, st);
+    e = launch_render(a, s.policy, false, test_mode(s), grid, block, st);
     if (e != hipSuccess)
         return hip_fail(e, "render launch");
     return MANDEL_OK;

@@ -26,6 +26,7 @@ struct GraphEntry {
     uint64_t *stats;
     int32_t probe_cap;
     int32_t workers;
+    int32_t periodicity;
     int64_t first_slot;
     hipGraph_t graph;
     hipGraphExec_t exec;
@@ -175,6 +176,7 @@ int enqueue(mandel_plan *p, int32_t *out, const mandel_launch &la, hipStream_t s
     sc.policy = policy;
     sc.waves_per_group = p->tune.waves_per_group;
     sc.workers = rows ? la.workers : p->tune.groups;
+    sc.periodicity = la.periodicity;
     dim3 grid, block;
     int rc = tile_grid(sc, true, p->ntiles, &grid, &block);
     if (rc)
@@ -183,7 +185,7 @@ int enqueue(mandel_plan *p, int32_t *out, const mandel_launch &la, hipStream_t s
                      la.tile_cost ? p->ntiles : 0, la.stats, s);
     if (e != hipSuccess)
         return hip_fail(e, "clear launch");
-    e = launch_render(a, policy, true, true, grid, block, s);
+    e = launch_render(a, policy, true, test_mode(sc), grid, block, s);
     if (e != hipSuccess)
         return hip_fail(e, "render launch");
     return MANDEL_OK;
@@ -303,6 +305,10 @@ int mandel_plan_launch(mandel_plan *p, int32_t *out, const mandel_launch *args, 
         return fail(MANDEL_EINVAL, "probe_cap=%d outside [1, 2^20]", la.probe_cap);
     if (la.first_slot < 0)
         return fail(MANDEL_EINVAL, "negative first_slot");
+    if (la.periodicity != 0 && la.periodicity != 1)
+        return fail(MANDEL_EINVAL, "periodicity must be 0 or 1");
+    if (la.reserved != 0)
+        return fail(MANDEL_EINVAL, "reserved field must be 0");
     if (p->ntiles == 0)
         return MANDEL_OK;
     if (!out)
@@ -319,7 +325,8 @@ int mandel_plan_launch(mandel_plan *p, int32_t *out, const mandel_launch *args, 
     for (const GraphEntry &g : p->graphs) {
         if (g.out == out && g.mode == la.mode && g.order == la.order && g.mlp == la.mlp &&
             g.tile_cost == la.tile_cost && g.stats == la.stats && g.probe_cap == la.probe_cap &&
-            g.workers == la.workers && g.first_slot == la.first_slot) {
+            g.workers == la.workers && g.periodicity == la.periodicity &&
+            g.first_slot == la.first_slot) {
             hipError_t e = hipGraphLaunch(g.exec, s);
             return e == hipSuccess ? MANDEL_OK : hip_fail(e, "hipGraphLaunch");
         }
@@ -333,6 +340,7 @@ int mandel_plan_launch(mandel_plan *p, int32_t *out, const mandel_launch *args, 
     g.stats = la.stats;
     g.probe_cap = la.probe_cap;
     g.workers = la.workers;
+    g.periodicity = la.periodicity;
     g.first_slot = la.first_slot;
     g.graph = nullptr;
     g.exec = nullptr;

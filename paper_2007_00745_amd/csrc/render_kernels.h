@@ -50,10 +50,18 @@ struct RenderArgs {
     uint64_t *stats;               // optional: uint64[8], see mandel_sched.stats
 };
 
-hipError_t launch_render(const RenderArgs &a, int policy, bool batch, bool defer, dim3 grid,
+// How the escape test is scheduled: after every update; in deferred blocks (lanes
+// inside the safe disk); deferred blocks plus exact periodicity detection.
+enum : int {
+    TESTS_EVERY_UPDATE = 0,
+    TESTS_DEFERRED = 1,
+    TESTS_DEFERRED_PERIODIC = 2,
+};
+
+hipError_t launch_render(const RenderArgs &a, int policy, bool batch, int tests, dim3 grid,
                          dim3 block, hipStream_t s);
 hipError_t launch_clear(unsigned long long *head, int64_t first_slot, int64_t *tile_cost,
                         int32_t *claims, int64_t ntiles, uint64_t *stats, hipStream_t s);
-int persistent_blocks_per_cu(int policy, bool batch, bool defer, int threads);
+int persistent_blocks_per_cu(int policy, bool batch, int tests, int threads);
 
 } // namespace mandel

@@ -164,9 +164,14 @@ __global__ void clear_kernel(unsigned long long *head, int64_t first_slot, int64
     }
 }
 
-template <int POLICY, bool BATCH, bool DEFER>
+// Periodicity detection compares this many of the last states of each deferred block
+// with the block-start state, so every cycle of period <= PERIOD_WINDOW is found.
+constexpr uint32_t PERIOD_WINDOW = 32;
+
+template <int POLICY, bool BATCH, bool DEFER, bool PERIODIC>
 __global__ void __launch_bounds__(1024) render_kernel(RenderArgs a)
 {
+    static_assert(DEFER || !PERIODIC, "periodicity detection runs in the deferred blocks");
     __shared__ int32_t lds_next_row;
     if constexpr (POLICY == POLICY_STATIC_ROWS || POLICY == POLICY_ALTERNATING_ROWS) {
         if (threadIdx.x == 0)
@@ -348,6 +353,7 @@ __global__ void __launch_bounds__(1024) render_kernel(RenderArgs a)
     int64_t ltile = 0;                // tile of the pixel (cost log)
     bool active = false, pending = false, safe = false;
     uint64_t acc = 0;                 // sum of counts finished by this lane
+    uint64_t skipped = 0;             // PERIODIC: updates not run thanks to a detected cycle
     uint32_t W = 0;                   // wave iteration counter (uniform)
 
     auto refill = [&]() {
@@ -481,18 +487,57 @@ __global__ void __launch_bounds__(1024) render_kernel(RenderArgs a)
                     const uint32_t L = budget < Kc ? budget : Kc;
                     xs = x;
                     ys = y;
-                    for (uint32_t u = 0; u < (L >> 2); ++u) {
-                        update();
-                        update();
-                        update();
-                        update();
+                    uint64_t pm = 0; // PERIODIC: lanes whose state returned to the block start
+                    if constexpr (PERIODIC) {
+                        // The last Q states of the block are compared bit for bit with
+                        // the block-start state: an orbit that has settled on a cycle of
+                        // period p <= Q returns to it at some k in (L - Q, L].
+                        const uint32_t Q = L < PERIOD_WINDOW ? L : PERIOD_WINDOW;
+                        const uint32_t L0 = L - Q;
+                        for (uint32_t u = 0; u < (L0 >> 2); ++u) {
+                            update();
+                            update();
+                            update();
+                            update();
+                        }
+                        for (uint32_t u = 0; u < (L0 & 3u); ++u)
+                            update();
+                        const uint64_t xb = (uint64_t)__double_as_longlong(xs);
+                        const uint64_t yb = (uint64_t)__double_as_longlong(ys);
+                        for (uint32_t u = 0; u < Q; ++u) {
+                            update();
+                            pm |= __builtin_amdgcn_ballot_w64((uint64_t)__double_as_longlong(x) == xb) &
+                                  __builtin_amdgcn_ballot_w64((uint64_t)__double_as_longlong(y) == yb);
+                        }
+                    } else {
+                        for (uint32_t u = 0; u < (L >> 2); ++u) {
+                            update();
+                            update();
+                            update();
+                            update();
+                        }
+                        for (uint32_t u = 0; u < (L & 3u); ++u)
+                            update();
                     }
-                    for (uint32_t u = 0; u < (L & 3u); ++u)
-                        update();
                     W += L;
                     budget -= L;
                     const double sq = x * x + y * y;
                     const uint64_t em = ballot(!(sq <= R2)) & amask;
+                    if constexpr (PERIODIC) {
+                        // A lane that did not escape in this block and met its block-start
+                        // state again is on an exact cycle of non-escaping states (an
+                        // escape inside the block would have left |z|^2 > R^2 at its end),
+                        // so it never escapes: its count is max_iter.
+                        const uint64_t pl = pm & ~em & ballot(active);
+                        if (pl != 0) {
+                            const bool mine = (pl >> lane) & 1u;
+                            if (mine)
+                                skipped += deadline - W;
+                            finalize(mine, false);
+                            if (em == 0 && (uint32_t)__popcll(~ballot(active)) >= R)
+                                break; // enough idle lanes: refill them
+                        }
+                    }
                     if (em != 0) {
                         if ((em >> lane) & 1u) {
                             // rewind to the block start and replay it with tests
@@ -582,56 +627,69 @@ __global__ void __launch_bounds__(1024) render_kernel(RenderArgs a)
             atomicAdd((unsigned long long *)&a.stats[3], (unsigned long long)taken);
             atomicMax((unsigned long long *)&a.stats[6], (unsigned long long)wall_clock64());
         }
+        if constexpr (PERIODIC) {
+            const uint64_t sk = wave_sum_u64(skipped);
+            if (lane == 0)
+                atomicAdd((unsigned long long *)&a.stats[7], (unsigned long long)sk);
+        }
     }
 }
 
 // ---- launch helpers (host) ---------------------------------------------------
 
-template <int POLICY, bool BATCH, bool DEFER>
+template <int POLICY, bool BATCH, bool DEFER, bool PERIODIC>
 static hipError_t launch_one(const RenderArgs &a, dim3 grid, dim3 block, hipStream_t s)
 {
-    hipLaunchKernelGGL((render_kernel<POLICY, BATCH, DEFER>), grid, block, 0, s, a);
+    hipLaunchKernelGGL((render_kernel<POLICY, BATCH, DEFER, PERIODIC>), grid, block, 0, s, a);
     return hipGetLastError();
 }
 
 template <int POLICY, bool BATCH>
-static hipError_t launch_defer(const RenderArgs &a, bool defer, dim3 grid, dim3 block,
-                               hipStream_t s)
+static hipError_t launch_mode(const RenderArgs &a, int tests, dim3 grid, dim3 block,
+                              hipStream_t s)
 {
-    return defer ? launch_one<POLICY, BATCH, true>(a, grid, block, s)
-                 : launch_one<POLICY, BATCH, false>(a, grid, block, s);
+    switch (tests) {
+    case TESTS_EVERY_UPDATE:
+        return launch_one<POLICY, BATCH, false, false>(a, grid, block, s);
+    case TESTS_DEFERRED:
+        return launch_one<POLICY, BATCH, true, false>(a, grid, block, s);
+    case TESTS_DEFERRED_PERIODIC:
+        return launch_one<POLICY, BATCH, true, true>(a, grid, block, s);
+    default:
+        return hipErrorInvalidValue;
+    }
 }
 
-hipError_t launch_render(const RenderArgs &a, int policy, bool batch, bool defer, dim3 grid,
+hipError_t launch_render(const RenderArgs &a, int policy, bool batch, int tests, dim3 grid,
                          dim3 block, hipStream_t s)
 {
     if (batch) {
         switch (policy) {
         case POLICY_FCFS_TILES:
-            return launch_defer<POLICY_FCFS_TILES, true>(a, defer, grid, block, s);
+            return launch_mode<POLICY_FCFS_TILES, true>(a, tests, grid, block, s);
         case POLICY_ORDERED_TILES:
-            return launch_defer<POLICY_ORDERED_TILES, true>(a, defer, grid, block, s);
+            return launch_mode<POLICY_ORDERED_TILES, true>(a, tests, grid, block, s);
         case POLICY_GRID_TILES:
-            return launch_defer<POLICY_GRID_TILES, true>(a, defer, grid, block, s);
+            return launch_mode<POLICY_GRID_TILES, true>(a, tests, grid, block, s);
         case POLICY_STATIC_ROWS:
-            return launch_defer<POLICY_STATIC_ROWS, true>(a, defer, grid, block, s);
+            return launch_mode<POLICY_STATIC_ROWS, true>(a, tests, grid, block, s);
         case POLICY_ALTERNATING_ROWS:
-            return launch_defer<POLICY_ALTERNATING_ROWS, true>(a, defer, grid, block, s);
+            return launch_mode<POLICY_ALTERNATING_ROWS, true>(a, tests, grid, block, s);
         default:
             return hipErrorInvalidValue;
         }
     }
     switch (policy) {
     case POLICY_FCFS_TILES:
-        return launch_defer<POLICY_FCFS_TILES, false>(a, defer, grid, block, s);
+        return launch_mode<POLICY_FCFS_TILES, false>(a, tests, grid, block, s);
     case POLICY_STATIC_ROWS:
-        return launch_defer<POLICY_STATIC_ROWS, false>(a, defer, grid, block, s);
+        return launch_mode<POLICY_STATIC_ROWS, false>(a, tests, grid, block, s);
     case POLICY_ALTERNATING_ROWS:
-        return launch_defer<POLICY_ALTERNATING_ROWS, false>(a, defer, grid, block, s);
+        return launch_mode<POLICY_ALTERNATING_ROWS, false>(a, tests, grid, block, s);
     case POLICY_ORDERED_TILES:
-        return launch_defer<POLICY_ORDERED_TILES, false>(a, defer, grid, block, s);
+        return launch_mode<POLICY_ORDERED_TILES, false>(a, tests, grid, block, s);
     case POLICY_GRID_TILES:
-        return launch_defer<POLICY_GRID_TILES, false>(a, defer, grid, block, s);
+        return launch_mode<POLICY_GRID_TILES, false>(a, tests, grid, block, s);
     default:
         return hipErrorInvalidValue;
     }
@@ -650,28 +708,32 @@ hipError_t launch_clear(unsigned long long *head, int64_t first_slot, int64_t *t
     return hipGetLastError();
 }
 
-int persistent_blocks_per_cu(int policy, bool batch, bool defer, int threads)
+int persistent_blocks_per_cu(int policy, bool batch, int tests, int threads)
 {
     int nb = 0;
     hipError_t e = hipErrorInvalidValue;
-#define MANDEL_OCC(P, B, D)                                                                    \
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, render_kernel<P, B, D>, threads, 0)
+#define MANDEL_OCC(P, B)                                                                       \
+    do {                                                                                       \
+        if (tests == TESTS_EVERY_UPDATE)                                                       \
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(                                  \
+                &nb, render_kernel<P, B, false, false>, threads, 0);                            \
+        else if (tests == TESTS_DEFERRED)                                                      \
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(                                  \
+                &nb, render_kernel<P, B, true, false>, threads, 0);                             \
+        else                                                                                   \
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(                                  \
+                &nb, render_kernel<P, B, true, true>, threads, 0);                              \
+    } while (0)
     if (batch) {
-        if (policy == POLICY_ORDERED_TILES) {
-            if (defer) MANDEL_OCC(POLICY_ORDERED_TILES, true, true);
-            else MANDEL_OCC(POLICY_ORDERED_TILES, true, false);
-        } else {
-            if (defer) MANDEL_OCC(POLICY_FCFS_TILES, true, true);
-            else MANDEL_OCC(POLICY_FCFS_TILES, true, false);
-        }
+        if (policy == POLICY_ORDERED_TILES)
+            MANDEL_OCC(POLICY_ORDERED_TILES, true);
+        else
+            MANDEL_OCC(POLICY_FCFS_TILES, true);
     } else {
-        if (policy == POLICY_ORDERED_TILES) {
-            if (defer) MANDEL_OCC(POLICY_ORDERED_TILES, false, true);
-            else MANDEL_OCC(POLICY_ORDERED_TILES, false, false);
-        } else {
-            if (defer) MANDEL_OCC(POLICY_FCFS_TILES, false, true);
-            else MANDEL_OCC(POLICY_FCFS_TILES, false, false);
-        }
+        if (policy == POLICY_ORDERED_TILES)
+            MANDEL_OCC(POLICY_ORDERED_TILES, false);
+        else
+            MANDEL_OCC(POLICY_FCFS_TILES, false);
     }
 #undef MANDEL_OCC
     if (e != hipSuccess || nb < 1)

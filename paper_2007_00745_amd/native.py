@@ -44,7 +44,7 @@ class Sched(ctypes.Structure):
                 ("young_iters", ctypes.c_int32), ("refill_lanes", ctypes.c_int32),
                 ("order", ctypes.c_void_p), ("tile_cost", ctypes.c_void_p),
                 ("claims", ctypes.c_void_p), ("stats", ctypes.c_void_p),
-                ("tile_parts", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("tile_parts", ctypes.c_int32), ("periodicity", ctypes.c_int32),
                 ("first_slot", ctypes.c_int64)]
 
 
@@ -70,7 +70,8 @@ class LaunchC(ctypes.Structure):
                 ("order", ctypes.c_void_p), ("mlp", ctypes.c_void_p),
                 ("tile_cost", ctypes.c_void_p), ("stats", ctypes.c_void_p),
                 ("probe_cap", ctypes.c_int32), ("workers", ctypes.c_int32),
-                ("first_slot", ctypes.c_int64)]
+                ("first_slot", ctypes.c_int64), ("periodicity", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 PLAN_MODES = {"fcfs": 0, "ordered": 1, "probe": 2, "learned": 3, "static": 4, "alternating": 5}
@@ -194,11 +195,12 @@ def render(window, m: int, n: int, max_iter: int, R: float, out=None, stream=Non
 
 def make_sched(policy="fcfs", tile_w=0, tile_h=0, grain=0, workers=0, waves_per_group=0,
                check_every=0, block_iters=0, young_iters=0, refill_lanes=0, order=None,
-               tile_cost=None, claims=None, stats=None, tile_parts=0, first_slot=0) -> Sched:
+               tile_cost=None, claims=None, stats=None, tile_parts=0, first_slot=0,
+               periodicity=0) -> Sched:
     pol = POLICIES[policy] if isinstance(policy, str) else int(policy)
     return Sched(pol, tile_w, tile_h, grain, workers, waves_per_group, check_every,
                  block_iters, young_iters, refill_lanes, _ptr(order), _ptr(tile_cost),
-                 _ptr(claims), _ptr(stats), tile_parts, 0, first_slot)
+                 _ptr(claims), _ptr(stats), tile_parts, int(periodicity), first_slot)
 
 
 def render_sched(window, m: int, n: int, max_iter: int, R: float, out=None, stream=None,
@@ -260,10 +262,10 @@ class Plan:
         return max((o + v.m * v.n for o, v in zip(self.out_offsets, self.views)), default=0)
 
     def launch(self, out, mode="fcfs", use_graph=False, order=None, mlp=None, tile_cost=None,
-               stats=None, probe_cap=0, first_slot=0, workers=0, stream=None):
+               stats=None, probe_cap=0, first_slot=0, workers=0, periodicity=0, stream=None):
         la = LaunchC(PLAN_MODES[mode] if isinstance(mode, str) else int(mode), int(use_graph),
                      _ptr(order), _ptr(mlp), _ptr(tile_cost), _ptr(stats), int(probe_cap),
-                     int(workers), int(first_slot))
+                     int(workers), int(first_slot), int(periodicity), 0)
         check(lib().mandel_plan_launch(self._h, _ptr(out), ctypes.byref(la), _stream(stream)))
         return out
 

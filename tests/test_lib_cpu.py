@@ -67,7 +67,7 @@ def test_empty_image_is_a_no_op():
     dict(waves_per_group=17), dict(check_every=2), dict(block_iters=70000), dict(young_iters=-1),
     dict(workers=-1), dict(refill_lanes=65), dict(refill_lanes=-2), dict(tile_parts=65),
     dict(tile_parts=-1), dict(first_slot=-1), dict(policy="static", workers=3, first_slot=2),
-    dict(policy="grid", first_slot=1),
+    dict(policy="grid", first_slot=1), dict(periodicity=2), dict(periodicity=1, check_every=1),
 ])
 def test_invalid_schedules(s):
     sched = native.make_sched(**s)
