@@ -11,13 +11,17 @@ value = pixel-iterations per second (sum of the counts / mean step time);
 FP64 FLOP/s counts 7 operations per iteration (x*x, y*y, x*y, 2*, -, +cx, +cy).
 
 Also reported (not the value): the plain mandel_render (FCFS queue in tile
-order) and the order by true tile costs on the same view; makespans on the
-uneven 64-view batch (seed 745) for per-view static rows (paper Sec. III-A),
-alternating rows (Sec. III-C), per-view FCFS and one batched launch in FCFS,
-probe-heuristic, learned and true-cost orders; the oracle's rate on the host
-cores for a bounded sample.
+order) and the order by true tile costs on the same view; the time to the same
+image with exact periodicity detection (updates skipped reported apart, never
+counted as executed); the paper's image shape (8000 x 8000, max_iter 2000,
+R 400, window assumed) next to the paper's 32-task computation time; makespans
+on the uneven 64-view batch (seed 745) for per-view static rows (paper
+Sec. III-A), alternating rows (Sec. III-C), per-view FCFS, the two row
+partitions as one launch over all rows of the batch, and one batched launch in
+FCFS, probe-heuristic, learned and true-cost orders; the oracle's rate on the
+host cores for a bounded sample and on one core for the 640 x 480 view.
 
-Prints one JSON line.  --gpus N > 1 is refused: this build runs on one GPU.
+Prints one JSON line.  --gpus N > 1 is refused: the benchmark runs on one GPU.
 """
 from __future__ import annotations
 
@@ -96,6 +100,27 @@ def cpu_baseline(view, rows_step: int, threads: int) -> dict:
 # Gold 6150 nodes, 8000 x 8000 image, iterationMax 2000, escape radius 400 (the five
 # runs of its appendix listing; the window is not stated).
 PAPER_ALT32_COMPUTE_S = (2.855784, 2.857663, 2.858120, 2.855122, 2.855696)
+
+
+def periodicity(torch, native, view, plan, out, sum_counts, headline_ms, clock_khz,
+                stream) -> dict:
+    """Time to the same image with exact periodicity detection (FCFS queue): lanes
+    whose FP64 state recurs bit for bit stop early with count max_iter.  Skipped
+    updates are reported, not counted as executed."""
+    ref = out.clone()
+    ms = timed_ms(torch, lambda: plan.launch(out, periodicity=1, use_graph=True, stream=stream),
+                  3, "periodicity detection")
+    assert torch.equal(out, ref), "periodicity detection changed the counts"
+    stats = torch.zeros(8, dtype=torch.int64, device="cuda")
+    plan.launch(out, periodicity=1, stats=stats, stream=stream)
+    torch.cuda.synchronize()
+    st = [int(v) for v in stats.cpu().tolist()]
+    executed = sum_counts - st[7]
+    return {"ms": ms, "sum_counts": sum_counts, "updates_skipped": st[7],
+            "updates_executed": executed,
+            "executed_pixel_iterations_per_s": executed / (ms / 1e3),
+            "time_to_image_speedup_vs_step": headline_ms / ms,
+            "tail": tail_fraction(st, clock_khz)}
 
 
 def paper_context(torch, native, workloads) -> dict:
@@ -332,7 +357,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print(json.dumps({"error": "this build runs on a single GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "the benchmark runs on a single GPU; --gpus must be 1"}))
         sys.exit(2)
 
     import torch
@@ -409,6 +434,7 @@ def main():
     render_tflops = FLOPS_PER_ITER * sum_counts / (render_ms / 1e3) / 1e12
     log(f"bench: ordered render alone {render_ms:.3f} ms, {render_tflops:.2f} TFLOP/s")
     comp = None
+    per = None
     kernels = None
     ceiling = None
     if not args.profile:
@@ -427,6 +453,7 @@ def main():
             f"{best:.1f} TFLOP/s")
         comp = comparisons(torch, native, view, plan, out, cost, sum_counts, stream)
         comp["render_kernel_ms"] = render_ms
+        per = periodicity(torch, native, view, plan, out, sum_counts, ms_mean, clock_khz, stream)
         import numpy as np
         f = plan.features().cpu().numpy()[:, 4:].astype(np.float64)
         cap = min(view.max_iter, 128)
@@ -478,6 +505,7 @@ def main():
         "comparisons": comp,
         "secondary_kernels": kernels,
         "fp64_ceiling": ceiling,
+        "periodicity_detection": per,
     }
     if not args.profile:
         res["paper_context"] = paper_context(torch, native, workloads)
