@@ -66,6 +66,44 @@ typedef struct mandel_window {
 int mandel_render(const mandel_window *w, int32_t m, int32_t n, int32_t max_iter,
                   double R, int32_t *out, void *stream);
 
+/*
+ * Deep zoom: the same escape-time count (Sec. I, Eq. (1)-(2)) evaluated in
+ * double-double arithmetic, for pixel pitches below binary64 resolution near c
+ * (about 1e-16 |c|), where neighbouring pixels would otherwise share one c.
+ * Each value is hi + lo of two binary64 numbers; the operations are Knuth's
+ * two-sum, Dekker's fast two-sum and the fma-based exact product, combined into
+ * the accurate addition and the products of Hida, Li and Bailey:
+ *   add(A, B)  (s, e) = two_sum(A.hi, B.hi); (t, f) = two_sum(A.lo, B.lo);
+ *              e = e + t; (s, e) = quick_two_sum(s, e); e = e + f;
+ *              (s, e) = quick_two_sum(s, e)
+ *   sqr(A)     (p, e) = two_prod(A.hi, A.hi); e = fma(A.hi + A.hi, A.lo, e);
+ *              quick_two_sum(p, e)
+ *   mul(A, B)  (p, e) = two_prod(A.hi, B.hi); e = fma(A.hi, B.lo, e);
+ *              e = fma(A.lo, B.hi, e); quick_two_sum(p, e)
+ * update: X' = add(add(sqr(X), -sqr(Y)), Cx),  Y' = add(2 mul(X, Y), Cy);
+ * a state escapes when fl(fl(X.hi^2) + fl(Y.hi^2)) > R^2; the count is the
+ * first escaping k >= 1, else max_iter.  Pixel centre (j, i):
+ *   Cx = add((cx0_hi, cx0_lo), two_prod((j + 0.5) - n/2, dx)), likewise Cy.
+ * Every operation is one binary64 rounding in this order, so counts are
+ * reproducible bit for bit on any IEEE machine with fma.
+ */
+typedef struct mandel_window_dd {
+    double cx0_hi, cx0_lo;   /* real part of the window centre, hi + lo */
+    double cy0_hi, cy0_lo;   /* imaginary part of the window centre, hi + lo */
+    double dx, dy;           /* pixel pitch (> 0), binary64 */
+} mandel_window_dd;
+
+/*
+ * mandel_render_dd -- deep-zoom counts of an m x n view into out (device
+ * int32[m*n], row-major, fully overwritten) on `stream`; persistent FCFS tile
+ * queue of 64 x 8 tiles.  stats: NULL or device uint64[4] accumulated over
+ * calls ([0] wavefront steps, [1] sum of counts, [2] wavefronts, [3] tiles).
+ * Same argument limits as mandel_render, and every pixel centre must lie within
+ * |re|, |im| <= 1e150.  Returns 0, or -1 EINVAL / -3 EHIP with nothing enqueued.
+ */
+int mandel_render_dd(const mandel_window_dd *w, int32_t m, int32_t n, int32_t max_iter,
+                     double R, int32_t *out, uint64_t *stats, void *stream);
+
 /* Work partitions of the kernel family (one kernel template, five sources of work). */
 enum mandel_policy {
     /* Sec. III-B, first come first served: a device-wide atomic queue of tiles,

@@ -9,7 +9,8 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libmandel.so")
-SOURCES = ["render_kernels.hip", "api.hip", "plan.hip", "costmodel.hip", "tune.hip", "probe.hip"]
+SOURCES = ["render_kernels.hip", "api.hip", "plan.hip", "costmodel.hip", "tune.hip", "probe.hip",
+           "dd_kernels.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

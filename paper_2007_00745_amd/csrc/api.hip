@@ -11,6 +11,7 @@
 #include <string>
 #include <utility>
 
+#include "dd_kernels.h"
 #include "mandel.h"
 #include "mandel_internal.h"
 #include "render_kernels.h"
@@ -359,6 +360,75 @@ int mandel_render(const mandel_window *w, int32_t m, int32_t n, int32_t max_iter
                   int32_t *out, void *stream)
 {
     return mandel_render_sched(w, m, n, max_iter, R, out, nullptr, stream);
+}
+
+int mandel_render_dd(const mandel_window_dd *w, int32_t m, int32_t n, int32_t max_iter,
+                     double R, int32_t *out, uint64_t *stats, void *stream)
+{
+    clear_error();
+    if (!w)
+        return fail(MANDEL_EINVAL, "window is NULL");
+    if (m < 0 || n < 0)
+        return fail(MANDEL_EINVAL, "negative size m=%d n=%d", m, n);
+    if ((int64_t)m * (int64_t)n >= (int64_t(1) << 40))
+        return fail(MANDEL_EINVAL, "image too large: %d x %d", m, n);
+    if (max_iter < 1 || max_iter > (1 << 30))
+        return fail(MANDEL_EINVAL, "max_iter=%d outside [1, 2^30]", max_iter);
+    if (!std::isfinite(R) || !(R > 0.0) || R > 1e150)
+        return fail(MANDEL_EINVAL, "escape radius R=%g outside (0, 1e150]", R);
+    const double v[6] = {w->cx0_hi, w->cx0_lo, w->cy0_hi, w->cy0_lo, w->dx, w->dy};
+    for (double x : v)
+        if (!std::isfinite(x))
+            return fail(MANDEL_EINVAL, "window has a non-finite value");
+    if (!(w->dx > 0.0) || !(w->dy > 0.0))
+        return fail(MANDEL_EINVAL, "pixel pitch must be > 0 (dx=%g dy=%g)", w->dx, w->dy);
+    // every pixel centre within |re|, |im| <= 1e150, so no square of a state that
+    // has not escaped can overflow
+    const double ex = std::fabs(w->cx0_hi) + std::fabs(w->cx0_lo) + 0.5 * (double)n * w->dx;
+    const double ey = std::fabs(w->cy0_hi) + std::fabs(w->cy0_lo) + 0.5 * (double)m * w->dy;
+    if (!(ex <= 1e150) || !(ey <= 1e150))
+        return fail(MANDEL_EINVAL, "window reaches beyond |c| = 1e150");
+    if (m == 0 || n == 0)
+        return MANDEL_OK;
+    if (!out)
+        return fail(MANDEL_EINVAL, "out is NULL");
+    hipStream_t st = (hipStream_t)stream;
+    unsigned long long *head = nullptr;
+    int rc = workspace_head(st, &head);
+    if (rc)
+        return rc;
+    int cus = 0;
+    rc = device_cus(&cus);
+    if (rc)
+        return rc;
+    DDArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.cx0h = w->cx0_hi;
+    a.cx0l = w->cx0_lo;
+    a.cy0h = w->cy0_hi;
+    a.cy0l = w->cy0_lo;
+    a.dx = w->dx;
+    a.dy = w->dy;
+    a.R2 = R * R;
+    a.m = m;
+    a.n = n;
+    a.max_iter = max_iter;
+    a.tile_w = 64;
+    a.tile_h = 8;
+    a.tiles_x = (n + 63) / 64;
+    a.ntiles = (int64_t)a.tiles_x * ((m + 7) / 8);
+    a.out = out;
+    a.head = head;
+    a.stats = stats;
+    const int threads = 256;
+    const dim3 grid((unsigned)(cus * dd_blocks_per_cu(threads))), block(threads);
+    hipError_t e = launch_clear(head, 0, nullptr, nullptr, 0, nullptr, st);
+    if (e != hipSuccess)
+        return hip_fail(e, "clear launch");
+    e = launch_render_dd(a, grid, block, st);
+    if (e != hipSuccess)
+        return hip_fail(e, "render launch");
+    return MANDEL_OK;
 }
 
 } // extern "C"

@@ -36,6 +36,12 @@ class Window(ctypes.Structure):
                 ("dx", ctypes.c_double), ("dy", ctypes.c_double)]
 
 
+class WindowDD(ctypes.Structure):
+    _fields_ = [("cx0_hi", ctypes.c_double), ("cx0_lo", ctypes.c_double),
+                ("cy0_hi", ctypes.c_double), ("cy0_lo", ctypes.c_double),
+                ("dx", ctypes.c_double), ("dy", ctypes.c_double)]
+
+
 class Sched(ctypes.Structure):
     _fields_ = [("policy", ctypes.c_int32), ("tile_w", ctypes.c_int32),
                 ("tile_h", ctypes.c_int32), ("grain", ctypes.c_int32),
@@ -104,6 +110,8 @@ def lib() -> ctypes.CDLL:
         P, i32, i64, d = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
         L.mandel_render.argtypes = [ctypes.POINTER(Window), i32, i32, i32, d, P, P]
         L.mandel_render.restype = ctypes.c_int
+        L.mandel_render_dd.argtypes = [ctypes.POINTER(WindowDD), i32, i32, i32, d, P, P, P]
+        L.mandel_render_dd.restype = ctypes.c_int
         L.mandel_render_sched.argtypes = [ctypes.POINTER(Window), i32, i32, i32, d, P,
                                           ctypes.POINTER(Sched), P]
         L.mandel_render_sched.restype = ctypes.c_int
@@ -190,6 +198,17 @@ def render(window, m: int, n: int, max_iter: int, R: float, out=None, stream=Non
     w = Window(*[float(v) for v in window])
     check(lib().mandel_render(ctypes.byref(w), m, n, int(max_iter), float(R), _ptr(out),
                               _stream(stream)))
+    return out
+
+
+def render_dd(window, m: int, n: int, max_iter: int, R: float, out=None, stats=None,
+              stream=None):
+    """mandel_render_dd: double-double deep-zoom counts.  window = (cx0_hi, cx0_lo,
+    cy0_hi, cy0_lo, dx, dy).  Returns the (m, n) int32 tensor."""
+    out = _out(out, m, n)
+    w = WindowDD(*[float(v) for v in window])
+    check(lib().mandel_render_dd(ctypes.byref(w), m, n, int(max_iter), float(R), _ptr(out),
+                                 _ptr(stats), _stream(stream)))
     return out
 
 

@@ -83,3 +83,25 @@ def test_fp64_probe_argument_checks():
                                    None) == native.EINVAL
     assert L.mandel_fp64_probe(0, 10, 1, None, ctypes.byref(fl), ctypes.byref(ms),
                                None) == native.EINVAL
+
+
+def _call_dd(win=(-0.5, 0.0, 0.0, 0.0, 0.01, 0.01), m=8, n=8, mi=10, R=2.0, out=0x1000):
+    w = native.WindowDD(*win)
+    return native.lib().mandel_render_dd(ctypes.byref(w), m, n, mi, R, out, None, None)
+
+
+@pytest.mark.parametrize("kw", [
+    dict(m=-1), dict(mi=0), dict(mi=(1 << 30) + 1), dict(R=0.0), dict(R=1e151),
+    dict(win=(float("nan"), 0.0, 0.0, 0.0, 0.01, 0.01)),
+    dict(win=(0.0, float("inf"), 0.0, 0.0, 0.01, 0.01)),
+    dict(win=(0.0, 0.0, 0.0, 0.0, 0.0, 0.01)), dict(win=(0.0, 0.0, 0.0, 0.0, 0.01, -1e-20)),
+    dict(win=(1e150, 0.0, 0.0, 0.0, 1e140, 0.01)), dict(m=1 << 20, n=1 << 20), dict(out=None),
+])
+def test_dd_invalid_arguments(kw):
+    assert _call_dd(**kw) == native.EINVAL
+    assert native.lib().mandel_last_error()
+
+
+def test_dd_empty_image_is_a_no_op():
+    assert _call_dd(m=0, out=None) == native.OK
+    assert native.lib().mandel_render_dd(None, 4, 4, 10, 2.0, 0x1000, None, None) == native.EINVAL
