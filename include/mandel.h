@@ -38,6 +38,7 @@ extern "C" {
 #define MANDEL_EINVAL (-1) /* bad argument: null pointer, bad size, non-finite value */
 #define MANDEL_ENOMEM (-2) /* device or host allocation failed */
 #define MANDEL_EHIP (-3)   /* HIP runtime error (launch, copy, graph) */
+#define MANDEL_EIO (-4)    /* host file could not be written */
 
 /*
  * The complex window.  Pixel (i, j) (row i, column j) of an m x n view maps to
@@ -103,6 +104,30 @@ typedef struct mandel_window_dd {
  */
 int mandel_render_dd(const mandel_window_dd *w, int32_t m, int32_t n, int32_t max_iter,
                      double R, int32_t *out, uint64_t *stats, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Output path (Sec. III: one process writes the image file; Sec. I with
+ * Eq. (2): each pixel's colour follows from its iteration count).
+ * ------------------------------------------------------------------------- */
+
+/*
+ * mandel_colour_boolean -- Boolean escape-time colouring on the device: pixel p
+ * becomes black (0, 0, 0) when counts[p] >= max_iter (it never escaped) and
+ * white (255, 255, 255) otherwise.  counts: device int32[npix]; rgb: device
+ * uint8[3 * npix], written as R, G, B per pixel in pixel order (the PPM P6
+ * layout).  Enqueued on `stream`.  Returns 0, or -1 EINVAL (npix < 0,
+ * max_iter < 1, NULL buffer) / -3 EHIP.
+ */
+int mandel_colour_boolean(const int32_t *counts, int64_t npix, int32_t max_iter, uint8_t *rgb,
+                          void *stream);
+
+/*
+ * mandel_write_ppm -- writes a binary PPM (P6, maxval 255) of an m-row,
+ * n-column image: the header "P6\n<n> <m>\n255\n", then rgb (host memory,
+ * 3 * m * n bytes, row-major) as is.  Synchronous host I/O; the file is
+ * replaced.  Returns 0, -1 EINVAL, or -4 EIO.
+ */
+int mandel_write_ppm(const char *path, const uint8_t *rgb, int32_t m, int32_t n);
 
 /* Work partitions of the kernel family (one kernel template, five sources of work). */
 enum mandel_policy {

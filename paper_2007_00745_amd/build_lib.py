@@ -10,7 +10,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libmandel.so")
 SOURCES = ["render_kernels.hip", "api.hip", "plan.hip", "costmodel.hip", "tune.hip", "probe.hip",
-           "dd_kernels.hip"]
+           "dd_kernels.hip", "output.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -14,6 +14,7 @@
 #include "dd_kernels.h"
 #include "mandel.h"
 #include "mandel_internal.h"
+#include "output.h"
 #include "render_kernels.h"
 
 namespace mandel {
@@ -360,6 +361,36 @@ int mandel_render(const mandel_window *w, int32_t m, int32_t n, int32_t max_iter
                   int32_t *out, void *stream)
 {
     return mandel_render_sched(w, m, n, max_iter, R, out, nullptr, stream);
+}
+
+int mandel_colour_boolean(const int32_t *counts, int64_t npix, int32_t max_iter, uint8_t *rgb,
+                          void *stream)
+{
+    clear_error();
+    if (npix < 0)
+        return fail(MANDEL_EINVAL, "negative pixel count");
+    if (max_iter < 1)
+        return fail(MANDEL_EINVAL, "max_iter=%d < 1", max_iter);
+    if (npix == 0)
+        return MANDEL_OK;
+    if (!counts || !rgb)
+        return fail(MANDEL_EINVAL, "counts or rgb is NULL");
+    hipError_t e = launch_colour(counts, npix, max_iter, rgb, (hipStream_t)stream);
+    return e == hipSuccess ? MANDEL_OK : hip_fail(e, "colour launch");
+}
+
+int mandel_write_ppm(const char *path, const uint8_t *rgb, int32_t m, int32_t n)
+{
+    clear_error();
+    if (!path)
+        return fail(MANDEL_EINVAL, "path is NULL");
+    if (m < 0 || n < 0)
+        return fail(MANDEL_EINVAL, "negative size m=%d n=%d", m, n);
+    if (!rgb && (int64_t)m * n > 0)
+        return fail(MANDEL_EINVAL, "rgb is NULL");
+    if (write_ppm(path, rgb, m, n) != 0)
+        return fail(MANDEL_EIO, "cannot write %s", path);
+    return MANDEL_OK;
 }
 
 int mandel_render_dd(const mandel_window_dd *w, int32_t m, int32_t n, int32_t max_iter,

@@ -16,7 +16,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libmandel.so")
 HEADER = os.path.join(os.path.dirname(PKG), "include", "mandel.h")
 
-OK, EINVAL, ENOMEM, EHIP = 0, -1, -2, -3
+OK, EINVAL, ENOMEM, EHIP, EIO = 0, -1, -2, -3, -4
 
 FCFS_TILES, STATIC_ROWS, ALTERNATING_ROWS, ORDERED_TILES, GRID_TILES = 0, 1, 2, 3, 4
 POLICIES = {
@@ -112,6 +112,10 @@ def lib() -> ctypes.CDLL:
         L.mandel_render.restype = ctypes.c_int
         L.mandel_render_dd.argtypes = [ctypes.POINTER(WindowDD), i32, i32, i32, d, P, P, P]
         L.mandel_render_dd.restype = ctypes.c_int
+        L.mandel_colour_boolean.argtypes = [P, i64, i32, P, P]
+        L.mandel_colour_boolean.restype = ctypes.c_int
+        L.mandel_write_ppm.argtypes = [ctypes.c_char_p, P, i32, i32]
+        L.mandel_write_ppm.restype = ctypes.c_int
         L.mandel_render_sched.argtypes = [ctypes.POINTER(Window), i32, i32, i32, d, P,
                                           ctypes.POINTER(Sched), P]
         L.mandel_render_sched.restype = ctypes.c_int
@@ -210,6 +214,24 @@ def render_dd(window, m: int, n: int, max_iter: int, R: float, out=None, stats=N
     check(lib().mandel_render_dd(ctypes.byref(w), m, n, int(max_iter), float(R), _ptr(out),
                                  _ptr(stats), _stream(stream)))
     return out
+
+
+def colour_boolean(counts, max_iter: int, rgb=None, stream=None):
+    """mandel_colour_boolean: device counts (int32, any shape) -> device RGB bytes,
+    shape counts.shape + (3,)."""
+    import torch
+    if rgb is None:
+        rgb = torch.empty(tuple(counts.shape) + (3,), dtype=torch.uint8, device=counts.device)
+    check(lib().mandel_colour_boolean(_ptr(counts), counts.numel(), int(max_iter), _ptr(rgb),
+                                      _stream(stream)))
+    return rgb
+
+
+def write_ppm(path: str, rgb, m: int, n: int) -> None:
+    """mandel_write_ppm: rgb is host memory (a contiguous CPU tensor or numpy array)
+    of 3 * m * n bytes."""
+    ptr = rgb.data_ptr() if hasattr(rgb, "data_ptr") else rgb.ctypes.data
+    check(lib().mandel_write_ppm(os.fsencode(path), ptr, int(m), int(n)))
 
 
 def make_sched(policy="fcfs", tile_w=0, tile_h=0, grain=0, workers=0, waves_per_group=0,
