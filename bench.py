@@ -123,6 +123,53 @@ def periodicity(torch, native, view, plan, out, sum_counts, headline_ms, clock_k
             "tail": tail_fraction(st, clock_khz)}
 
 
+def output_path(torch, native, out, view, step, stream) -> dict:
+    """The paper's total-time analog: the headline step, then Boolean colouring,
+    the copy to pinned host memory and the PPM write (to a temporary directory),
+    each timed; plus an 8-frame zoom sequence written sequentially and with the
+    writes overlapped with the next frame's render."""
+    import shutil
+    import tempfile
+
+    from paper_2007_00745_amd import output, workloads
+    npx = view.pixels
+    rgb = torch.empty(3 * npx, dtype=torch.uint8, device="cuda")
+    host = torch.empty(3 * npx, dtype=torch.uint8, pin_memory=True)
+    colour_ms = timed_ms(torch, lambda: native.colour_boolean(out, view.max_iter, rgb,
+                                                              stream=stream), 3, "colour")
+    copy_ms = timed_ms(torch, lambda: host.copy_(rgb, non_blocking=True), 3, "copy to host")
+    tmp = tempfile.mkdtemp(prefix="mandel_ppm_")
+    try:
+        t0 = time.perf_counter()
+        native.write_ppm(os.path.join(tmp, "c2.ppm"), host, view.m, view.n)
+        write_s = time.perf_counter() - t0
+        # total, end to end: step -> colour -> copy -> write
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        step()
+        native.colour_boolean(out, view.max_iter, rgb, stream=stream)
+        host.copy_(rgb, non_blocking=True)
+        torch.cuda.synchronize()
+        native.write_ppm(os.path.join(tmp, "c2.ppm"), host, view.m, view.n)
+        total_s = time.perf_counter() - t0
+        frames = [workloads.View((SEAHORSE[0], SEAHORSE[1], 4e-3 / 4096 / 2 ** k,
+                                  4e-3 / 4096 / 2 ** k), 4096, 4096, 5000) for k in range(8)]
+        seq = {}
+        for pipelined in (False, True):
+            paths = [os.path.join(tmp, f"f{k}.ppm") for k in range(len(frames))]
+            seq["pipelined" if pipelined else "sequential"] = output.render_to_ppm(
+                frames, paths, pipelined=pipelined)
+    finally:
+        shutil.rmtree(tmp, ignore_errors=True)
+    gbs = 7.0 * npx / (colour_ms / 1e3) / 1e9
+    return {"image": f"{view.m}x{view.n}", "colour_ms": colour_ms,
+            "colour_kernel": {"bound": "hbm", "bytes_per_pixel": 7, "achieved_gbs": gbs,
+                              "frac": gbs / HBM_PEAK_GBS},
+            "copy_to_host_ms": copy_ms, "copy_gbs": 3.0 * npx / (copy_ms / 1e3) / 1e9,
+            "ppm_write_s": write_s, "total_time_s": total_s,
+            "zoom_sequence_8x4096sq": seq}
+
+
 # FP64 instructions of one double-double update + test: 72 add/sub, 5 mul, 7 fma
 DD_INSTR_PER_ITER = 84
 DD_FLOPS_PER_ITER = 72 + 5 + 2 * 7
@@ -470,6 +517,7 @@ def main():
     log(f"bench: ordered render alone {render_ms:.3f} ms, {render_tflops:.2f} TFLOP/s")
     comp = None
     per = None
+    outp = None
     kernels = None
     ceiling = None
     if not args.profile:
@@ -489,6 +537,7 @@ def main():
         comp = comparisons(torch, native, view, plan, out, cost, sum_counts, stream)
         comp["render_kernel_ms"] = render_ms
         per = periodicity(torch, native, view, plan, out, sum_counts, ms_mean, clock_khz, stream)
+        outp = output_path(torch, native, out, view, step, stream)
         import numpy as np
         f = plan.features().cpu().numpy()[:, 4:].astype(np.float64)
         cap = min(view.max_iter, 128)
@@ -541,6 +590,7 @@ def main():
         "secondary_kernels": kernels,
         "fp64_ceiling": ceiling,
         "periodicity_detection": per,
+        "output_path": outp,
     }
     if not args.profile:
         res["paper_context"] = paper_context(torch, native, workloads)
