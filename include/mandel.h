@@ -20,7 +20,9 @@
  *   - stream is a hipStream_t (NULL = the legacy default stream).  Calls
  *     enqueue work and return; results are valid once the stream is
  *     synchronised.  Calls on the same stream run in order; the library keeps
- *     one small workspace (queue head, counters) per (device, stream).
+ *     one small workspace (a 256-byte queue head and a 32 KiB order histogram)
+ *     per (device, stream) it has seen, until the process ends.  Calls that
+ *     overlap in time on different streams never share a workspace.
  *   - Return value: MANDEL_OK (0) or a negative code.  On error nothing is
  *     enqueued, and mandel_last_error() returns a description (thread-local).
  *     No C++ exception crosses this interface.
