@@ -286,8 +286,10 @@ enum mandel_plan_mode {
 typedef struct mandel_launch {
     int32_t mode;            /* enum mandel_plan_mode */
     int32_t use_graph;       /* 1: capture the launch sequence once into a hipGraph
-                                (keyed by every pointer below and out_base) and
-                                replay it; 0: enqueue the kernels directly */
+                                (keyed by every field below and out_base; each
+                                distinct key keeps its graph until
+                                mandel_plan_destroy) and replay it; 0: enqueue the
+                                kernels directly */
     const int32_t *order;    /* device int32[ntiles], ORDERED: a permutation of tile ids */
     const float *mlp;        /* device float[MANDEL_MLP_PARAMS], LEARNED_LPT: the cost model */
     int64_t *tile_cost;      /* device int64[ntiles] or NULL: sum of counts per tile */
