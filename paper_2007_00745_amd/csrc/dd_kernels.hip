@@ -22,7 +22,7 @@
 // Work distribution: persistent wavefronts claim tiles from a device-wide
 // atomic queue (the analogue of the paper's first-come-first-served rows,
 // Sec. III-B); lanes whose pixel finished take the next pixels of the tile
-// (ballot + mbcnt) once 16 lanes are idle.  Each update is about 60 FP64
+// (ballot + mbcnt) once 4 lanes are idle.  Each update is about 84 FP64
 // operations, so the test after every update costs little and no deferred
 // blocks are used.
 #include <hip/hip_runtime.h>
@@ -84,7 +84,7 @@ __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v)
     return v;
 }
 
-constexpr uint32_t DD_REFILL_LANES = 16; // idle lanes that trigger a refill round
+constexpr uint32_t DD_REFILL_LANES = 4; // idle lanes that trigger a refill round (swept: 4, 8, 16)
 
 } // namespace
 
