@@ -573,6 +573,9 @@ def main():
         "fp64_tflops": tflops,
         "pct_fp64_peak": 100.0 * tflops / FP64_PEAK_TFLOPS,
         "lane_occupancy": lane_occ,
+        # the device queue replaces the paper's FCFS messages (2 per row, Eq. (fcfs_m))
+        "queue_claims_per_step": st[3],
+        "paper_fcfs_messages_same_rows": 2 * view.m,
         "tail": tail_fraction(st, clock_khz),
         "ms_min": min(ms),
         "ms_median": sorted(ms)[len(ms) // 2],
