@@ -63,3 +63,11 @@ def test_colour_argument_checks():
     assert L.mandel_colour_boolean(0x1000, 8, 0, 0x2000, None) == native.EINVAL
     assert L.mandel_colour_boolean(None, 8, 10, 0x2000, None) == native.EINVAL
     assert L.mandel_colour_boolean(0x1000, 0, 10, None, None) == native.OK
+
+
+def test_cli_argument_errors():
+    from paper_2007_00745_amd import __main__ as cli
+    with pytest.raises(SystemExit):
+        cli.main(["--centre", "0", "0"])                      # no pitch
+    with pytest.raises(SystemExit):
+        cli.main(["--double-double", "--schedule", "static"])
