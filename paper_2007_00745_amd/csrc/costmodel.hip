@@ -30,7 +30,11 @@ constexpr int OFF_B3 = OFF_W3 + NH;
 static_assert(OFF_B3 + 1 == MANDEL_MLP_PARAMS, "parameter layout");
 constexpr int NTRAIN = MANDEL_MLP_PARAMS - MANDEL_MLP_NORM; // 8641
 
-__device__ __forceinline__ int32_t find_view_b(const ViewDesc *views, int32_t nviews, int64_t t)
+// The view table is never written by these kernels: read as constant memory, a
+// wave-uniform descriptor comes through the scalar cache into SGPRs.
+typedef const __attribute__((address_space(4))) ViewDesc ConstViewDesc;
+
+__device__ __forceinline__ int32_t find_view_b(ConstViewDesc *views, int32_t nviews, int64_t t)
 {
     int32_t lo = 0, hi = nviews - 1;
     while (lo < hi) {
@@ -49,12 +53,15 @@ __global__ void __launch_bounds__(256) features_kernel(const ViewDesc *views, in
                                                        int32_t tile_h, int32_t probe_cap,
                                                        float *feat)
 {
-    const int64_t t = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x / 64);
+    // one tile per wavefront: t is the same in all 64 lanes
+    const int64_t t = (int64_t)blockIdx.x * (blockDim.x / 64) +
+                      (int64_t)__builtin_amdgcn_readfirstlane(threadIdx.x / 64);
     if (t >= ntiles)
         return;
     const int lane = threadIdx.x & 63;
-    const int32_t v = find_view_b(views, nviews, t);
-    const ViewDesc vd = views[v];
+    ConstViewDesc *table = (ConstViewDesc *)views;
+    const int32_t v = find_view_b(table, nviews, t);
+    ConstViewDesc &vd = table[v];
     const int32_t lt = (int32_t)(t - vd.tile_off); // a plan has fewer than 2^31 tiles
     const int32_t ty = lt / vd.tiles_x;
     const int32_t tx = lt - ty * vd.tiles_x;
@@ -73,20 +80,37 @@ __global__ void __launch_bounds__(256) features_kernel(const ViewDesc *views, in
     const double cy = vd.cy0 + py;
     const int32_t cap = vd.max_iter < probe_cap ? vd.max_iter : probe_cap;
     // min(count, cap): test z_{k-1} before forming z_k, reusing its squares; the
-    // test of z_cap is not needed because the count is capped at cap anyway.
+    // test of z_cap is not needed because the count is capped at cap anyway.  Four
+    // tested updates per round without branches; a lane that escaped keeps its
+    // count and its (unused) state runs on; the wave stops when no lane is live.
+    const double R2 = vd.R2;
     double x = 0.0, y = 0.0;
     int32_t cnt = cap;
-    for (int32_t k = 1; k <= cap; ++k) {
+    bool live = true;
+    auto tested = [&](int32_t it) { // test z_{it-1}, then form z_it
         const double xx = x * x;
         const double yy = y * y;
-        if (xx + yy > vd.R2) {
-            cnt = k - 1;
-            break;
-        }
+        const bool esc = live && xx + yy > R2;
+        cnt = esc ? it - 1 : cnt;
+        live = live && !esc;
         const double tt = x * y;
         x = (xx - yy) + cx;
         y = __builtin_fma(2.0, tt, cy);
+    };
+    int32_t it = 1;
+    bool any = true;
+    for (; it + 3 <= cap; it += 4) {
+        tested(it);
+        tested(it + 1);
+        tested(it + 2);
+        tested(it + 3);
+        if (__builtin_amdgcn_ballot_w64(live) == 0) {
+            any = false;
+            break;
+        }
     }
+    for (; any && it <= cap; ++it)
+        tested(it);
     float *f = feat + t * NF;
     f[4 + lane] = logf(1.0f + (float)cnt) / logf(1.0f + (float)cap);
     if (lane < 4) {
