@@ -1,0 +1,59 @@
+"""Host-side runtime helpers around the library: a persistent autotune cache and
+a stream watchdog.
+
+* ``autotune_cached(views, path)`` -- the library caches autotune results per
+  device and batch signature for the life of the process; this keeps them in a
+  JSON file across processes, keyed by the device name and the batch signature
+  (sizes, max_iter and radius of every view, sorted), so a batch seen before is
+  not re-timed.
+* ``wait(stream, timeout)`` -- polls a stream until its work is done or the time
+  runs out (then raises TimeoutError, leaving the work running): a host watchdog
+  for callers that must not block forever on a device call.
+"""
+from __future__ import annotations
+
+import hashlib
+import json
+import os
+import time
+
+from . import native
+
+
+def batch_signature(views) -> str:
+    items = sorted((v.m, v.n, v.max_iter, float(v.R).hex()) for v in views)
+    return hashlib.sha256(json.dumps(items).encode()).hexdigest()[:24]
+
+
+def autotune_cached(views, path: str, max_sample: int = 8, device_name: str | None = None,
+                    stream=None) -> tuple[dict, bool]:
+    """(tuning, came_from_file).  The file is rewritten atomically on a miss."""
+    if device_name is None:
+        import torch
+        device_name = torch.cuda.get_device_name()
+    key = f"{device_name}|{batch_signature(views)}"
+    table = {}
+    if os.path.exists(path):
+        with open(path) as f:
+            table = json.load(f)
+    if key in table:
+        return dict(table[key]), True
+    tuning, _ = native.autotune(views, max_sample=max_sample, stream=stream)
+    table[key] = tuning
+    tmp = f"{path}.tmp{os.getpid()}"
+    with open(tmp, "w") as f:
+        json.dump(table, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+    return tuning, False
+
+
+def wait(stream, timeout: float, poll: float = 1e-3) -> float:
+    """Returns the seconds waited once stream.query() is true; raises TimeoutError
+    after `timeout` seconds."""
+    t0 = time.perf_counter()
+    while not stream.query():
+        waited = time.perf_counter() - t0
+        if waited > timeout:
+            raise TimeoutError(f"stream still busy after {waited:.3f} s")
+        time.sleep(poll)
+    return time.perf_counter() - t0

@@ -1,0 +1,49 @@
+"""Host runtime helpers on the CPU: the autotune cache file (a hit never calls
+the library, a miss writes the file) and the stream watchdog (returns when the
+stream drains, raises on timeout)."""
+import json
+
+import pytest
+
+from paper_2007_00745_amd import native, runtime, workloads
+
+
+class _FakeStream:
+    def __init__(self, busy_polls):
+        self.left = busy_polls
+
+    def query(self):
+        self.left -= 1
+        return self.left < 0
+
+
+def test_watchdog_returns_and_times_out():
+    assert runtime.wait(_FakeStream(3), timeout=1.0, poll=1e-4) >= 0.0
+    with pytest.raises(TimeoutError):
+        runtime.wait(_FakeStream(10 ** 9), timeout=0.02, poll=1e-3)
+
+
+def test_signature_ignores_order_and_window():
+    a = [workloads.View((0.0, 0.0, 1e-3, 1e-3), 10, 20, 100), workloads.c1()]
+    b = [workloads.c1(), workloads.View((0.5, 0.1, 1e-4, 1e-4), 10, 20, 100)]
+    assert runtime.batch_signature(a) == runtime.batch_signature(b)
+    c = [workloads.c1(), workloads.View((0.0, 0.0, 1e-3, 1e-3), 10, 20, 101)]
+    assert runtime.batch_signature(a) != runtime.batch_signature(c)
+
+
+def test_autotune_cache_file(tmp_path, monkeypatch):
+    views = [workloads.c1()]
+    calls = []
+
+    def fake_autotune(v, max_sample=8, stream=None):
+        calls.append(len(v))
+        return {"tile_w": 32, "tile_h": 4}, 15
+
+    monkeypatch.setattr(native, "autotune", fake_autotune)
+    path = str(tmp_path / "tune.json")
+    t1, hit1 = runtime.autotune_cached(views, path, device_name="dev0")
+    t2, hit2 = runtime.autotune_cached(views, path, device_name="dev0")
+    t3, hit3 = runtime.autotune_cached(views, path, device_name="dev1")
+    assert (hit1, hit2, hit3) == (False, True, False) and calls == [1, 1]
+    assert t1 == t2 == t3 == {"tile_w": 32, "tile_h": 4}
+    assert len(json.load(open(path))) == 2
