@@ -102,6 +102,31 @@ def cpu_baseline(view, rows_step: int, threads: int) -> dict:
 PAPER_ALT32_COMPUTE_S = (2.855784, 2.857663, 2.858120, 2.855122, 2.855696)
 
 
+def tail_analysis(torch, native, plan, out, params, cost, clock_khz, stream, last=64) -> dict:
+    """One learned launch with per-tile timestamps: which tiles finish last, how
+    their true cost and predicted cost rank among all tiles (percentiles, 100 = most
+    expensive), and how long before the queue ran dry they were claimed."""
+    import numpy as np
+    nt = plan.ntiles
+    tt = torch.zeros(2 * nt, dtype=torch.int64, device="cuda")
+    stats = torch.zeros(8, dtype=torch.int64, device="cuda")
+    plan.launch(out, mode="learned", mlp=params, tile_time=tt, stats=stats, stream=stream)
+    keys = native.mlp_forward(params, plan.features(stream=stream), stream=stream)
+    torch.cuda.synchronize()
+    t = tt.cpu().numpy().view(np.uint64).reshape(nt, 2).astype(np.float64)
+    st = stats.cpu().numpy().view(np.uint64).astype(np.float64)
+    c = cost.cpu().numpy()
+    k = keys.cpu().numpy()
+    pct = lambda a: 100.0 * np.argsort(np.argsort(a)) / max(nt - 1, 1)
+    cp, kp = pct(c), pct(k)
+    idx = np.argsort(t[:, 1])[-last:]
+    return {"last_tiles": last,
+            "true_cost_percentile_mean": float(cp[idx].mean()),
+            "predicted_percentile_mean": float(kp[idx].mean()),
+            "claimed_ms_before_queue_dry_mean": float(((st[5] - t[idx, 0]) / clock_khz).mean()),
+            "finished_ms_after_queue_dry_max": float(((t[idx, 1] - st[5]) / clock_khz).max())}
+
+
 def periodicity(torch, native, view, plan, out, sum_counts, headline_ms, clock_khz,
                 stream) -> dict:
     """Time to the same image with exact periodicity detection (FCFS queue): lanes
@@ -537,6 +562,9 @@ def main():
         comp = comparisons(torch, native, view, plan, out, cost, sum_counts, stream)
         comp["render_kernel_ms"] = render_ms
         per = periodicity(torch, native, view, plan, out, sum_counts, ms_mean, clock_khz, stream)
+        if params is not None:
+            comp["tail_analysis"] = tail_analysis(torch, native, plan, out, params, cost,
+                                                  clock_khz, stream)
         outp = output_path(torch, native, out, view, step, stream)
         import numpy as np
         f = plan.features().cpu().numpy()[:, 4:].astype(np.float64)

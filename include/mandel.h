@@ -204,6 +204,11 @@ typedef struct mandel_sched {
                                 slots are skipped and their pixels left untouched,
                                 so a launch can resume after slot k or cover only
                                 part of the queue; >= 0 [0]; must be 0 otherwise */
+    uint64_t *tile_time;     /* tile policies: NULL, or device uint64[2 * ntiles] cleared
+                                by the call: [2t] the first claim of tile t, [2t + 1]
+                                the moment its last pixel finished (wall-clock ticks,
+                                as stats[4..6]); for tail analysis -- it adds an
+                                atomic per pixel.  Must be NULL for row policies. */
 } mandel_sched;
 
 /*
@@ -304,6 +309,9 @@ typedef struct mandel_launch {
                                 in mandel_sched [0] */
     int32_t periodicity;     /* 1: exact periodicity detection, as in mandel_sched [0] */
     int32_t reserved;        /* must be 0 */
+    uint64_t *tile_time;     /* device uint64[2 * ntiles] or NULL: per-tile first claim
+                                and last finished pixel, as in mandel_sched; queue
+                                modes only */
 } mandel_launch;
 
 /*

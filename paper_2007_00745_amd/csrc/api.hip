@@ -58,7 +58,7 @@ int workspace_head(hipStream_t s, unsigned long long **head)
     std::lock_guard<std::mutex> lk(g_ws_mu);
     Workspace &w = g_ws[{dev, s}];
     if (!w.head) {
-        e = hipMalloc((void **)&w.head, 256);
+        e = hipMalloc((void **)&w.head, HEAD_BYTES);
         if (e != hipSuccess) {
             w.head = nullptr;
             return fail(MANDEL_ENOMEM, "hipMalloc(workspace): %s", hipGetErrorString(e));
@@ -212,6 +212,8 @@ int check_sched(const mandel_sched *s, mandel_sched *o)
         return fail(MANDEL_EINVAL, "negative first_slot");
     if (d.first_slot != 0 && d.policy != MANDEL_FCFS_TILES && d.policy != MANDEL_ORDERED_TILES)
         return fail(MANDEL_EINVAL, "first_slot applies to the queue policies only");
+    if (d.tile_time && (d.policy == MANDEL_STATIC_ROWS || d.policy == MANDEL_ALTERNATING_ROWS))
+        return fail(MANDEL_EINVAL, "tile_time applies to the tile policies only");
     if (d.policy == MANDEL_ORDERED_TILES && !d.order)
         return fail(MANDEL_EINVAL, "ORDERED_TILES needs an order array");
     *o = d;
@@ -330,6 +332,7 @@ int mandel_render_sched(const mandel_window *w, int32_t m, int32_t n, int32_t ma
     a.order = s.order;
     a.tile_cost = rows ? nullptr : s.tile_cost;
     a.claims = s.claims;
+    a.tile_time = s.tile_time;
     a.stats = s.stats;
 
     unsigned long long *head = nullptr;
@@ -347,8 +350,9 @@ int mandel_render_sched(const mandel_window *w, int32_t m, int32_t n, int32_t ma
         if (rc)
             return rc;
     }
-    hipError_t e = launch_clear(head, s.first_slot, a.tile_cost, a.claims,
-                                a.tile_cost || a.claims ? ntiles : 0, a.stats, st);
+    hipError_t e = launch_clear(head, s.first_slot, a.tile_cost, a.claims, a.tile_time,
+                                a.tile_cost || a.claims || a.tile_time ? ntiles : 0, a.stats,
+                                st);
     if (e != hipSuccess)
         return hip_fail(e, "clear launch");
     e = launch_render(a, s.policy, false, test_mode(s), grid, block, st);
@@ -453,7 +457,7 @@ int mandel_render_dd(const mandel_window_dd *w, int32_t m, int32_t n, int32_t ma
     a.stats = stats;
     const int threads = 256;
     const dim3 grid((unsigned)(cus * dd_blocks_per_cu(threads))), block(threads);
-    hipError_t e = launch_clear(head, 0, nullptr, nullptr, 0, nullptr, st);
+    hipError_t e = launch_clear(head, 0, nullptr, nullptr, nullptr, 0, nullptr, st);
     if (e != hipSuccess)
         return hip_fail(e, "clear launch");
     e = launch_render_dd(a, grid, block, st);

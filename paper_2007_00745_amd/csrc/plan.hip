@@ -28,6 +28,7 @@ struct GraphEntry {
     int32_t workers;
     int32_t periodicity;
     int64_t first_slot;
+    uint64_t *tile_time;
     hipGraph_t graph;
     hipGraphExec_t exec;
 };
@@ -169,6 +170,7 @@ int enqueue(mandel_plan *p, int32_t *out, const mandel_launch &la, hipStream_t s
     a.order = order;
     a.tile_cost = la.tile_cost;
     a.claims = nullptr;
+    a.tile_time = la.tile_time;
     a.stats = la.stats;
 
     mandel_sched sc;
@@ -182,7 +184,7 @@ int enqueue(mandel_plan *p, int32_t *out, const mandel_launch &la, hipStream_t s
     if (rc)
         return rc;
     e = launch_clear(rows ? nullptr : p->d_head, la.first_slot, la.tile_cost, nullptr,
-                     la.tile_cost ? p->ntiles : 0, la.stats, s);
+                     la.tile_time, la.tile_cost || la.tile_time ? p->ntiles : 0, la.stats, s);
     if (e != hipSuccess)
         return hip_fail(e, "clear launch");
     e = launch_render(a, policy, true, test_mode(sc), grid, block, s);
@@ -245,7 +247,7 @@ int mandel_plan_create(const mandel_view *views, int32_t nviews, const mandel_tu
         e = hipMemcpy(p->d_views, p->views.data(), sizeof(ViewDesc) * (size_t)nviews,
                       hipMemcpyHostToDevice);
     if (e == hipSuccess)
-        e = hipMalloc((void **)&p->d_head, 256);
+        e = hipMalloc((void **)&p->d_head, HEAD_BYTES);
     if (e == hipSuccess)
         e = hipStreamCreateWithFlags(&p->capture, hipStreamNonBlocking);
     if (e != hipSuccess) {
@@ -285,8 +287,9 @@ int mandel_plan_launch(mandel_plan *p, int32_t *out, const mandel_launch *args, 
     if (rows) {
         if (la.workers < 1)
             return fail(MANDEL_EINVAL, "row modes need workers >= 1");
-        if (la.tile_cost)
-            return fail(MANDEL_EINVAL, "row modes log no tile costs (tile_cost must be NULL)");
+        if (la.tile_cost || la.tile_time)
+            return fail(MANDEL_EINVAL, "row modes log no per-tile data (tile_cost and tile_time "
+                                       "must be NULL)");
         if (la.first_slot != 0)
             return fail(MANDEL_EINVAL, "row modes have no queue (first_slot must be 0)");
         if (p->nrows >= ((int64_t)1 << 31))
@@ -326,7 +329,7 @@ int mandel_plan_launch(mandel_plan *p, int32_t *out, const mandel_launch *args, 
         if (g.out == out && g.mode == la.mode && g.order == la.order && g.mlp == la.mlp &&
             g.tile_cost == la.tile_cost && g.stats == la.stats && g.probe_cap == la.probe_cap &&
             g.workers == la.workers && g.periodicity == la.periodicity &&
-            g.first_slot == la.first_slot) {
+            g.first_slot == la.first_slot && g.tile_time == la.tile_time) {
             hipError_t e = hipGraphLaunch(g.exec, s);
             return e == hipSuccess ? MANDEL_OK : hip_fail(e, "hipGraphLaunch");
         }
@@ -342,6 +345,7 @@ int mandel_plan_launch(mandel_plan *p, int32_t *out, const mandel_launch *args, 
     g.workers = la.workers;
     g.periodicity = la.periodicity;
     g.first_slot = la.first_slot;
+    g.tile_time = la.tile_time;
     g.graph = nullptr;
     g.exec = nullptr;
     hipError_t e = hipStreamBeginCapture(p->capture, hipStreamCaptureModeThreadLocal);

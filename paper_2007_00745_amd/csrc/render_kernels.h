@@ -13,6 +13,9 @@ enum : int {
     POLICY_GRID_TILES = 4,
 };
 
+// Bytes of a queue head allocation (one 64-bit counter on its own 256-byte line).
+constexpr int HEAD_BYTES = 256;
+
 // One view as the kernels see it (96 bytes).
 struct ViewDesc {
     double cx0, cy0, dx, dy; // window: centre and pixel pitch
@@ -47,6 +50,7 @@ struct RenderArgs {
     const int32_t *order;          // ORDERED: queue slot -> tile id
     int64_t *tile_cost;            // optional: sum of counts per tile
     int32_t *claims;               // optional: claims per tile
+    uint64_t *tile_time;           // optional: per tile, first claim and last pixel finished
     uint64_t *stats;               // optional: uint64[8], see mandel_sched.stats
 };
 
@@ -61,7 +65,8 @@ enum : int {
 hipError_t launch_render(const RenderArgs &a, int policy, bool batch, int tests, dim3 grid,
                          dim3 block, hipStream_t s);
 hipError_t launch_clear(unsigned long long *head, int64_t first_slot, int64_t *tile_cost,
-                        int32_t *claims, int64_t ntiles, uint64_t *stats, hipStream_t s);
+                        int32_t *claims, uint64_t *tile_time, int64_t ntiles, uint64_t *stats,
+                        hipStream_t s);
 int persistent_blocks_per_cu(int policy, bool batch, int tests, int threads);
 
 } // namespace mandel

@@ -144,7 +144,8 @@ __device__ __forceinline__ int32_t find_view(const ViewDesc *table, int32_t nvie
 
 // Clears the queue head and the optional per-tile logs before a launch.
 __global__ void clear_kernel(unsigned long long *head, int64_t first_slot, int64_t *tile_cost,
-                             int32_t *claims, int64_t ntiles, uint64_t *stats)
+                             int32_t *claims, uint64_t *tile_time, int64_t ntiles,
+                             uint64_t *stats)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -161,6 +162,10 @@ __global__ void clear_kernel(unsigned long long *head, int64_t first_slot, int64
             tile_cost[t] = 0;
         if (claims)
             claims[t] = 0;
+        if (tile_time) {
+            tile_time[2 * t] = ~0ull; // first claim (atomic min)
+            tile_time[2 * t + 1] = 0; // last pixel finished (atomic max)
+        }
     }
 }
 
@@ -270,6 +275,9 @@ __global__ void __launch_bounds__(1024) render_kernel(RenderArgs a)
                     continue; // empty part (a tile with fewer rows than parts)
                 if (a.claims && lane == 0)
                     atomicAdd(&a.claims[t], 1);
+                if (a.tile_time && lane == 0)
+                    atomicMin((unsigned long long *)&a.tile_time[2 * t],
+                              (unsigned long long)wall_clock64());
                 s_view = v;
                 s_x0 = x0;
                 s_y0 = y0 + r0;
@@ -432,6 +440,9 @@ __global__ void __launch_bounds__(1024) render_kernel(RenderArgs a)
             a.out[oidx] = (int32_t)cnt;
             if (a.tile_cost)
                 atomicAdd((unsigned long long *)&a.tile_cost[ltile], (unsigned long long)cnt);
+            if (a.tile_time)
+                atomicMax((unsigned long long *)&a.tile_time[2 * ltile + 1],
+                          (unsigned long long)wall_clock64());
             acc += cnt;
             active = false;
             pending = false;
@@ -592,6 +603,9 @@ __global__ void __launch_bounds__(1024) render_kernel(RenderArgs a)
                     if (a.tile_cost)
                         atomicAdd((unsigned long long *)&a.tile_cost[ltile],
                                   (unsigned long long)cnt);
+                    if (a.tile_time)
+                        atomicMax((unsigned long long *)&a.tile_time[2 * ltile + 1],
+                                  (unsigned long long)wall_clock64());
                     acc += cnt;
                     active = false;
                     pending = false;
@@ -696,7 +710,8 @@ hipError_t launch_render(const RenderArgs &a, int policy, bool batch, int tests,
 }
 
 hipError_t launch_clear(unsigned long long *head, int64_t first_slot, int64_t *tile_cost,
-                        int32_t *claims, int64_t ntiles, uint64_t *stats, hipStream_t s)
+                        int32_t *claims, uint64_t *tile_time, int64_t ntiles, uint64_t *stats,
+                        hipStream_t s)
 {
     int64_t blocks = (ntiles + 255) / 256;
     if (blocks < 1)
@@ -704,7 +719,7 @@ hipError_t launch_clear(unsigned long long *head, int64_t first_slot, int64_t *t
     if (blocks > 4096)
         blocks = 4096;
     hipLaunchKernelGGL(clear_kernel, dim3((unsigned)blocks), dim3(256), 0, s, head, first_slot,
-                       tile_cost, claims, ntiles, stats);
+                       tile_cost, claims, tile_time, ntiles, stats);
     return hipGetLastError();
 }
 

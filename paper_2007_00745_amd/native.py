@@ -51,7 +51,7 @@ class Sched(ctypes.Structure):
                 ("order", ctypes.c_void_p), ("tile_cost", ctypes.c_void_p),
                 ("claims", ctypes.c_void_p), ("stats", ctypes.c_void_p),
                 ("tile_parts", ctypes.c_int32), ("periodicity", ctypes.c_int32),
-                ("first_slot", ctypes.c_int64)]
+                ("first_slot", ctypes.c_int64), ("tile_time", ctypes.c_void_p)]
 
 
 class ViewC(ctypes.Structure):
@@ -77,7 +77,7 @@ class LaunchC(ctypes.Structure):
                 ("tile_cost", ctypes.c_void_p), ("stats", ctypes.c_void_p),
                 ("probe_cap", ctypes.c_int32), ("workers", ctypes.c_int32),
                 ("first_slot", ctypes.c_int64), ("periodicity", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("reserved", ctypes.c_int32), ("tile_time", ctypes.c_void_p)]
 
 
 PLAN_MODES = {"fcfs": 0, "ordered": 1, "probe": 2, "learned": 3, "static": 4, "alternating": 5}
@@ -237,11 +237,12 @@ def write_ppm(path: str, rgb, m: int, n: int) -> None:
 def make_sched(policy="fcfs", tile_w=0, tile_h=0, grain=0, workers=0, waves_per_group=0,
                check_every=0, block_iters=0, young_iters=0, refill_lanes=0, order=None,
                tile_cost=None, claims=None, stats=None, tile_parts=0, first_slot=0,
-               periodicity=0) -> Sched:
+               periodicity=0, tile_time=None) -> Sched:
     pol = POLICIES[policy] if isinstance(policy, str) else int(policy)
     return Sched(pol, tile_w, tile_h, grain, workers, waves_per_group, check_every,
                  block_iters, young_iters, refill_lanes, _ptr(order), _ptr(tile_cost),
-                 _ptr(claims), _ptr(stats), tile_parts, int(periodicity), first_slot)
+                 _ptr(claims), _ptr(stats), tile_parts, int(periodicity), first_slot,
+                 _ptr(tile_time))
 
 
 def render_sched(window, m: int, n: int, max_iter: int, R: float, out=None, stream=None,
@@ -303,10 +304,11 @@ class Plan:
         return max((o + v.m * v.n for o, v in zip(self.out_offsets, self.views)), default=0)
 
     def launch(self, out, mode="fcfs", use_graph=False, order=None, mlp=None, tile_cost=None,
-               stats=None, probe_cap=0, first_slot=0, workers=0, periodicity=0, stream=None):
+               stats=None, probe_cap=0, first_slot=0, workers=0, periodicity=0, tile_time=None,
+               stream=None):
         la = LaunchC(PLAN_MODES[mode] if isinstance(mode, str) else int(mode), int(use_graph),
                      _ptr(order), _ptr(mlp), _ptr(tile_cost), _ptr(stats), int(probe_cap),
-                     int(workers), int(first_slot), int(periodicity), 0)
+                     int(workers), int(first_slot), int(periodicity), 0, _ptr(tile_time))
         check(lib().mandel_plan_launch(self._h, _ptr(out), ctypes.byref(la), _stream(stream)))
         return out
 

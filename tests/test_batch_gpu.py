@@ -152,6 +152,25 @@ def test_plan_tile_cost_and_stats(small_batch):
     plan.close()
 
 
+def test_plan_tile_timestamps(small_batch):
+    # learned mode with graph replays: every tile stamped, claim before finish
+    views, want = small_batch
+    plan = native.Plan(views)
+    tt = torch.zeros(2 * plan.ntiles, dtype=torch.int64, device="cuda")
+    params = torch.tensor(_params(3, plan.features()), dtype=torch.float32, device="cuda")
+    out = torch.empty((plan.out_size(),), dtype=torch.int32, device="cuda")
+    for use_graph in (False, True, True):
+        tt.fill_(3)
+        plan.launch(out, mode="learned", mlp=params, tile_time=tt, use_graph=use_graph)
+        torch.cuda.synchronize()
+        _check(plan, out, want)
+        t = tt.cpu().numpy().view(np.uint64).reshape(plan.ntiles, 2)
+        assert (t[:, 0] <= t[:, 1]).all() and (t[:, 1] > 3).all()
+    with pytest.raises(native.MandelError):
+        plan.launch(out, mode="static", workers=4, tile_time=tt)
+    plan.close()
+
+
 def test_single_view_plan_equals_render():
     v = workloads.c1()
     plan = native.Plan([v])

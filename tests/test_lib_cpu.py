@@ -74,6 +74,17 @@ def test_invalid_schedules(s):
     assert _call(sched=sched) == native.EINVAL
 
 
+class _FakeDevicePtr:
+    def data_ptr(self):
+        return 0x2000
+
+
+@pytest.mark.parametrize("policy", ["static", "alternating"])
+def test_tile_time_rejected_for_row_policies(policy):
+    sched = native.make_sched(policy=policy, workers=4, tile_time=_FakeDevicePtr())
+    assert _call(sched=sched) == native.EINVAL
+
+
 def test_fp64_probe_argument_checks():
     L = native.lib()
     fl, ms = ctypes.c_double(), ctypes.c_float()

@@ -255,6 +255,27 @@ def test_forced_queue_start(c1_ref):
         assert np.array_equal(got, want), (policy, parts, k)
 
 
+@pytest.mark.parametrize("policy,parts", [("fcfs", 1), ("fcfs", 4), ("ordered", 1), ("grid", 1)])
+def test_tile_timestamps(c1_ref, policy, parts):
+    # per tile: first claim <= last finished pixel, both inside the launch's span;
+    # every tile is claimed; counts unchanged
+    v = workloads.c1()
+    nt = native.tile_count(v.m, v.n, 64, 8)
+    tt = torch.full((2 * nt,), 7, dtype=torch.int64, device="cuda")
+    stats = torch.zeros(8, dtype=torch.int64, device="cuda")
+    kw = dict(order=torch.randperm(nt).to(torch.int32).cuda()) if policy == "ordered" else {}
+    out = native.render_sched(v.window, v.m, v.n, v.max_iter, v.R, policy=policy, tile_parts=parts,
+                              tile_time=tt, stats=stats, **kw)
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy(), c1_ref)
+    t = tt.cpu().numpy().view(np.uint64).reshape(nt, 2)
+    st = stats.cpu().numpy().view(np.uint64)
+    assert (t[:, 0] <= t[:, 1]).all() and (t[:, 1] > 0).all()
+    assert (t[:, 1] <= st[6]).all()
+    if policy != "grid":  # the grid launch sets no first-claim stamp
+        assert (t[:, 0] >= st[4]).all()
+
+
 def test_concurrent_streams(c1_ref):
     # each (device, stream) has its own queue head, so calls on different streams may
     # overlap; two plans (each with its own head) may overlap too
