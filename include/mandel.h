@@ -312,6 +312,15 @@ typedef struct mandel_launch {
     uint64_t *tile_time;     /* device uint64[2 * ntiles] or NULL: per-tile first claim
                                 and last finished pixel, as in mandel_sched; queue
                                 modes only */
+    int32_t steal;           /* queue modes with tile_parts 1: 1 = row stealing.  The
+                                rows of a claimed tile are taken one at a time through
+                                a per-tile counter, and once the queue is empty a
+                                wavefront takes untaken rows of tiles that other
+                                wavefronts hold (wavefronts of one SIMD issue unevenly,
+                                so a tile claimed early can otherwise finish last).
+                                Every row is still rendered once; counts, cost logs and
+                                statistics are unchanged.  0: off [0] */
+    int32_t reserved2;       /* must be 0 */
 } mandel_launch;
 
 /*

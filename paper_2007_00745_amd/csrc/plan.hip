@@ -29,6 +29,7 @@ struct GraphEntry {
     int32_t periodicity;
     int64_t first_slot;
     uint64_t *tile_time;
+    int32_t steal;
     hipGraph_t graph;
     hipGraphExec_t exec;
 };
@@ -49,6 +50,10 @@ struct mandel_plan {
     float *d_keys = nullptr;
     int32_t *d_perm = nullptr;
     uint32_t *d_hist = nullptr;
+    // buffers of row stealing (allocated on first use)
+    int32_t *d_chunk = nullptr;
+    int32_t *d_active = nullptr;
+    int64_t active_len = 0;
     hipStream_t capture = nullptr;
     std::vector<GraphEntry> graphs;
 };
@@ -118,15 +123,73 @@ int ensure_order_buffers(mandel_plan *p, bool need_feat)
     return MANDEL_OK;
 }
 
+// Render policy of a plan launch mode.
+int mode_policy(int32_t mode)
+{
+    switch (mode) {
+    case MANDEL_PLAN_ORDERED:
+    case MANDEL_PLAN_PROBE_LPT:
+    case MANDEL_PLAN_LEARNED_LPT:
+        return POLICY_ORDERED_TILES;
+    case MANDEL_PLAN_STATIC_ROWS:
+        return POLICY_STATIC_ROWS;
+    case MANDEL_PLAN_ALTERNATING_ROWS:
+        return POLICY_ALTERNATING_ROWS;
+    default:
+        return POLICY_FCFS_TILES;
+    }
+}
+
+// Schedule and launch geometry of the render launch of a plan launch.
+int render_grid(mandel_plan *p, const mandel_launch &la, mandel_sched *sc, dim3 *grid,
+                dim3 *block)
+{
+    const int policy = mode_policy(la.mode);
+    const bool rows = policy == POLICY_STATIC_ROWS || policy == POLICY_ALTERNATING_ROWS;
+    std::memset(sc, 0, sizeof *sc);
+    sc->policy = policy;
+    sc->waves_per_group = p->tune.waves_per_group;
+    sc->workers = rows ? la.workers : p->tune.groups;
+    sc->periodicity = la.periodicity;
+    return tile_grid(*sc, true, p->ntiles, grid, block);
+}
+
+// Row counters (one per tile) and the held-tile table (one entry per wavefront of
+// the launch la will make), grown as needed.
+int ensure_steal_buffers(mandel_plan *p, const mandel_launch &la)
+{
+    mandel_sched sc;
+    dim3 grid, block;
+    int rc = render_grid(p, la, &sc, &grid, &block);
+    if (rc)
+        return rc;
+    const int64_t waves = (int64_t)grid.x * (block.x / 64);
+    hipError_t e;
+    if (!p->d_chunk) {
+        e = hipMalloc((void **)&p->d_chunk, sizeof(int32_t) * (size_t)p->ntiles);
+        if (e != hipSuccess)
+            return fail(MANDEL_ENOMEM, "hipMalloc(row counters): %s", hipGetErrorString(e));
+    }
+    if (p->active_len < waves) {
+        (void)hipFree(p->d_active);
+        p->d_active = nullptr;
+        p->active_len = 0;
+        e = hipMalloc((void **)&p->d_active, sizeof(int32_t) * (size_t)waves);
+        if (e != hipSuccess)
+            return fail(MANDEL_ENOMEM, "hipMalloc(held tiles): %s", hipGetErrorString(e));
+        p->active_len = waves;
+    }
+    return MANDEL_OK;
+}
+
 // Enqueues the whole launch sequence of one plan launch on stream s.
 int enqueue(mandel_plan *p, int32_t *out, const mandel_launch &la, hipStream_t s)
 {
     hipError_t e;
     const int32_t *order = nullptr;
-    int policy = POLICY_FCFS_TILES;
+    const int policy = mode_policy(la.mode);
     if (la.mode == MANDEL_PLAN_ORDERED) {
         order = la.order;
-        policy = POLICY_ORDERED_TILES;
     } else if (la.mode == MANDEL_PLAN_PROBE_LPT || la.mode == MANDEL_PLAN_LEARNED_LPT) {
         e = launch_features(p->d_views, (int32_t)p->views.size(), p->ntiles, p->tune.tile_w,
                             p->tune.tile_h, la.probe_cap, p->d_feat, s);
@@ -142,11 +205,6 @@ int enqueue(mandel_plan *p, int32_t *out, const mandel_launch &la, hipStream_t s
         if (e != hipSuccess)
             return hip_fail(e, "order launch");
         order = p->d_perm;
-        policy = POLICY_ORDERED_TILES;
-    } else if (la.mode == MANDEL_PLAN_STATIC_ROWS) {
-        policy = POLICY_STATIC_ROWS;
-    } else if (la.mode == MANDEL_PLAN_ALTERNATING_ROWS) {
-        policy = POLICY_ALTERNATING_ROWS;
     }
     const bool rows = policy == POLICY_STATIC_ROWS || policy == POLICY_ALTERNATING_ROWS;
 
@@ -171,20 +229,21 @@ int enqueue(mandel_plan *p, int32_t *out, const mandel_launch &la, hipStream_t s
     a.tile_cost = la.tile_cost;
     a.claims = nullptr;
     a.tile_time = la.tile_time;
+    a.steal = la.steal;
+    a.chunk = la.steal ? p->d_chunk : nullptr;
+    a.active = la.steal ? p->d_active : nullptr;
     a.stats = la.stats;
 
     mandel_sched sc;
-    std::memset(&sc, 0, sizeof sc);
-    sc.policy = policy;
-    sc.waves_per_group = p->tune.waves_per_group;
-    sc.workers = rows ? la.workers : p->tune.groups;
-    sc.periodicity = la.periodicity;
     dim3 grid, block;
-    int rc = tile_grid(sc, true, p->ntiles, &grid, &block);
+    int rc = render_grid(p, la, &sc, &grid, &block);
     if (rc)
         return rc;
+    if (la.steal && (int64_t)grid.x * (block.x / 64) > p->active_len)
+        return fail(MANDEL_EINVAL, "held-tile table smaller than the launch");
     e = launch_clear(rows ? nullptr : p->d_head, la.first_slot, la.tile_cost, nullptr,
-                     la.tile_time, la.tile_cost || la.tile_time ? p->ntiles : 0, la.stats, s);
+                     la.tile_time, la.tile_cost || la.tile_time || la.steal ? p->ntiles : 0,
+                     la.stats, s, a.chunk, a.active, la.steal ? p->active_len : 0);
     if (e != hipSuccess)
         return hip_fail(e, "clear launch");
     e = launch_render(a, policy, true, test_mode(sc), grid, block, s);
@@ -298,6 +357,8 @@ int mandel_plan_launch(mandel_plan *p, int32_t *out, const mandel_launch *args, 
     } else if (la.workers != 0) {
         return fail(MANDEL_EINVAL, "workers applies to the row modes only");
     }
+    if (rows && la.steal)
+        return fail(MANDEL_EINVAL, "row stealing applies to the queue modes only");
     if (la.mode == MANDEL_PLAN_ORDERED && !la.order)
         return fail(MANDEL_EINVAL, "ORDERED needs an order array");
     if (la.mode == MANDEL_PLAN_LEARNED_LPT && !la.mlp)
@@ -312,12 +373,25 @@ int mandel_plan_launch(mandel_plan *p, int32_t *out, const mandel_launch *args, 
         return fail(MANDEL_EINVAL, "periodicity must be 0 or 1");
     if (la.reserved != 0)
         return fail(MANDEL_EINVAL, "reserved field must be 0");
+    if (la.steal != 0 && la.steal != 1)
+        return fail(MANDEL_EINVAL, "steal must be 0 or 1");
+    if (la.reserved2 != 0)
+        return fail(MANDEL_EINVAL, "reserved2 must be 0");
+    if (la.steal && p->tune.tile_parts != 1)
+        return fail(MANDEL_EINVAL, "row stealing needs tile_parts 1");
+    if (la.steal && p->ntiles > INT32_MAX)
+        return fail(MANDEL_EINVAL, "row stealing supports at most 2^31 - 1 tiles");
     if (p->ntiles == 0)
         return MANDEL_OK;
     if (!out)
         return fail(MANDEL_EINVAL, "out_base is NULL");
-    if (la.mode >= MANDEL_PLAN_PROBE_LPT) {
+    if (la.mode == MANDEL_PLAN_PROBE_LPT || la.mode == MANDEL_PLAN_LEARNED_LPT) {
         int rc = ensure_order_buffers(p, true);
+        if (rc)
+            return rc;
+    }
+    if (la.steal) {
+        int rc = ensure_steal_buffers(p, la);
         if (rc)
             return rc;
     }
@@ -329,7 +403,8 @@ int mandel_plan_launch(mandel_plan *p, int32_t *out, const mandel_launch *args, 
         if (g.out == out && g.mode == la.mode && g.order == la.order && g.mlp == la.mlp &&
             g.tile_cost == la.tile_cost && g.stats == la.stats && g.probe_cap == la.probe_cap &&
             g.workers == la.workers && g.periodicity == la.periodicity &&
-            g.first_slot == la.first_slot && g.tile_time == la.tile_time) {
+            g.first_slot == la.first_slot && g.tile_time == la.tile_time &&
+            g.steal == la.steal) {
             hipError_t e = hipGraphLaunch(g.exec, s);
             return e == hipSuccess ? MANDEL_OK : hip_fail(e, "hipGraphLaunch");
         }
@@ -346,6 +421,7 @@ int mandel_plan_launch(mandel_plan *p, int32_t *out, const mandel_launch *args, 
     g.periodicity = la.periodicity;
     g.first_slot = la.first_slot;
     g.tile_time = la.tile_time;
+    g.steal = la.steal;
     g.graph = nullptr;
     g.exec = nullptr;
     hipError_t e = hipStreamBeginCapture(p->capture, hipStreamCaptureModeThreadLocal);
@@ -406,6 +482,8 @@ int mandel_plan_destroy(mandel_plan *p)
     (void)hipFree(p->d_keys);
     (void)hipFree(p->d_perm);
     (void)hipFree(p->d_hist);
+    (void)hipFree(p->d_chunk);
+    (void)hipFree(p->d_active);
     delete p;
     return MANDEL_OK;
 }

@@ -51,6 +51,10 @@ struct RenderArgs {
     int64_t *tile_cost;            // optional: sum of counts per tile
     int32_t *claims;               // optional: claims per tile
     uint64_t *tile_time;           // optional: per tile, first claim and last pixel finished
+    int32_t steal;                 // FCFS / ORDERED with parts 1: rows are taken through
+                                   // chunk[] and shared out once the queue is dry
+    int32_t *chunk;                // steal: next untaken row per tile [ntiles]
+    int32_t *active;               // steal: tile held by each wavefront [waves in grid]
     uint64_t *stats;               // optional: uint64[8], see mandel_sched.stats
 };
 
@@ -64,9 +68,12 @@ enum : int {
 
 hipError_t launch_render(const RenderArgs &a, int policy, bool batch, int tests, dim3 grid,
                          dim3 block, hipStream_t s);
+// Clears the queue head and the optional logs; with chunk/active (row stealing) also
+// the per-tile row counters [ntiles] and the per-wave held tiles [nwaves].
 hipError_t launch_clear(unsigned long long *head, int64_t first_slot, int64_t *tile_cost,
                         int32_t *claims, uint64_t *tile_time, int64_t ntiles, uint64_t *stats,
-                        hipStream_t s);
+                        hipStream_t s, int32_t *chunk = nullptr, int32_t *active = nullptr,
+                        int64_t nwaves = 0);
 int persistent_blocks_per_cu(int policy, bool batch, int tests, int threads);
 
 } // namespace mandel

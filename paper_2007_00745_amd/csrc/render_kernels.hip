@@ -145,7 +145,7 @@ __device__ __forceinline__ int32_t find_view(const ViewDesc *table, int32_t nvie
 // Clears the queue head and the optional per-tile logs before a launch.
 __global__ void clear_kernel(unsigned long long *head, int64_t first_slot, int64_t *tile_cost,
                              int32_t *claims, uint64_t *tile_time, int64_t ntiles,
-                             uint64_t *stats)
+                             uint64_t *stats, int32_t *chunk, int32_t *active, int64_t nwaves)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -166,17 +166,28 @@ __global__ void clear_kernel(unsigned long long *head, int64_t first_slot, int64
             tile_time[2 * t] = ~0ull; // first claim (atomic min)
             tile_time[2 * t + 1] = 0; // last pixel finished (atomic max)
         }
+        if (chunk)
+            chunk[t] = 0;
     }
+    for (int64_t w = i; active && w < nwaves; w += stride)
+        active[w] = -1;
 }
 
 // Periodicity detection compares this many of the last states of each deferred block
 // with the block-start state, so every cycle of period <= PERIOD_WINDOW is found.
 constexpr uint32_t PERIOD_WINDOW = 32;
 
-template <int POLICY, bool BATCH, bool DEFER, bool PERIODIC>
-__global__ void __launch_bounds__(1024) render_kernel(RenderArgs a)
+// Row stealing: a wave stops looking for rows to steal after this many takes that
+// found their tile already drained by others.
+constexpr int32_t STEAL_MAX_MISSES = 64;
+
+template <int POLICY, bool BATCH, bool DEFER, bool PERIODIC, bool STEAL>
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(STEAL ? 7 : 1)))
+render_kernel(RenderArgs a)
 {
     static_assert(DEFER || !PERIODIC, "periodicity detection runs in the deferred blocks");
+    static_assert(!STEAL || POLICY == POLICY_FCFS_TILES || POLICY == POLICY_ORDERED_TILES,
+                  "row stealing works on the tile queue");
     __shared__ int32_t lds_next_row;
     if constexpr (POLICY == POLICY_STATIC_ROWS || POLICY == POLICY_ALTERNATING_ROWS) {
         if (threadIdx.x == 0)
@@ -194,9 +205,151 @@ __global__ void __launch_bounds__(1024) render_kernel(RenderArgs a)
     int64_t s_tile = 0;          // tile id (for the cost log)
     int64_t q_next = 0;          // FCFS: next queue slot of the current claim
     int32_t q_left = 0;          // FCFS: slots left in the current claim
+    // STEAL: the tile whose rows this wave takes (-1: none), and the scan position
+    // and length over the other waves' tiles once the queue is dry (-1: not yet dry)
+    int32_t r_tile = -1;
+    int32_t r_scan = -1, r_scanned = 0, r_miss = 0;
     int32_t taken = 0;           // items taken (statistics)
     bool exhausted = false;
     bool grid_done = false;
+
+    // Geometry of tile t: its view and its clipped rectangle.
+    auto tile_geometry = [&](int64_t t, int32_t &v, int32_t &x0, int32_t &y0, int32_t &w,
+                             int32_t &h) {
+        int64_t tile_off;
+        int32_t tiles_x, vm, vn;
+        v = 0;
+        if constexpr (BATCH) {
+            v = bcast_i32(find_view(a.views, a.nviews, t));
+            const auto *vd = as_const(a.views) + v;
+            tile_off = vd->tile_off;
+            tiles_x = vd->tiles_x;
+            vm = vd->m;
+            vn = vd->n;
+        } else {
+            tile_off = a.v0.tile_off;
+            tiles_x = a.v0.tiles_x;
+            vm = a.v0.m;
+            vn = a.v0.n;
+        }
+        const int64_t lt = t - tile_off;
+        const int32_t ty = (int32_t)(lt / tiles_x);
+        const int32_t tx = (int32_t)(lt - (int64_t)ty * tiles_x);
+        x0 = tx * a.tile_w;
+        y0 = ty * a.tile_h;
+        w = vn - x0 < a.tile_w ? vn - x0 : a.tile_w;
+        h = vm - y0 < a.tile_h ? vm - y0 : a.tile_h;
+    };
+
+    // Row stealing.  A claimed tile's rows are handed out one at a time by its own
+    // counter a.chunk[t]; the claiming wave takes them in turn.  Once the queue is
+    // dry, a wave looks through the tiles the other waves hold (a.active, one entry
+    // per wave) for rows nobody has taken yet and takes them, so the rows of a tile
+    // held by a wave that issues slowly are shared out instead of finishing last.
+    // Every row is taken exactly once (one atomic increment per take), so counts,
+    // cost logs and timestamps are as without stealing.  The held-tile table and the
+    // counters are read and written with device-scope atomics: each XCD has its own
+    // L2, and a plain load could keep returning a line that another XCD has since
+    // changed.  A wave that holds a tile always takes its rows until none is left,
+    // so a thief may give up at any time; it gives up after a full pass of the table
+    // without a candidate, or after STEAL_MAX_MISSES takes that came too late.
+    auto steal_item = [&]() -> bool {
+        const int64_t nslots = a.ntiles;
+        const int32_t G = (int32_t)(gridDim.x * (blockDim.x >> 6));
+        const int32_t gw = (int32_t)(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
+        for (;;) {
+            if (r_tile >= 0) {
+                int32_t c = 0;
+                if (lane == 0)
+                    c = atomicAdd(&a.chunk[r_tile], 1);
+                c = bcast_i32(c);
+                int32_t v, x0, y0, w, h;
+                tile_geometry(r_tile, v, x0, y0, w, h);
+                if (c < h) {
+                    s_view = v;
+                    s_x0 = x0;
+                    s_y0 = y0 + c;
+                    s_w = w;
+                    s_next = 0;
+                    s_in = 0;
+                    s_jn = 0;
+                    s_cnt = w;
+                    s_tile = r_tile;
+                    return true;
+                }
+                r_tile = -1;
+                if (r_scan >= 0)
+                    ++r_miss; // a stolen take that found the tile already drained
+            }
+            if (r_scan < 0) {
+                // claim the next tile from the queue
+                if (q_left == 0) {
+                    unsigned long long q = 0;
+                    if (lane == 0)
+                        q = atomicAdd(a.head, (unsigned long long)a.grain);
+                    const int64_t qb = bcast_i64((int64_t)q);
+                    if (a.stats && lane == 0) {
+                        if (qb == a.first_slot)
+                            atomicMin((unsigned long long *)&a.stats[4],
+                                      (unsigned long long)wall_clock64());
+                        if (qb >= nslots && qb < nslots + a.grain)
+                            atomicMin((unsigned long long *)&a.stats[5],
+                                      (unsigned long long)wall_clock64());
+                    }
+                    if (qb >= nslots) {
+                        r_scan = 0; // the queue is dry: steal from now on
+                        continue;
+                    }
+                    q_next = qb;
+                    const int64_t left = nslots - qb;
+                    q_left = (int32_t)(left < a.grain ? left : a.grain);
+                }
+                const int64_t slot = q_next++;
+                --q_left;
+                int64_t t;
+                if constexpr (POLICY == POLICY_ORDERED_TILES) {
+                    t = (int64_t)as_const(a.order)[slot];
+                    if (t < 0 || t >= a.ntiles)
+                        continue; // not a tile id: skipped, never dereferenced
+                } else {
+                    t = slot;
+                }
+                if (a.claims && lane == 0)
+                    atomicAdd(&a.claims[t], 1);
+                if (a.tile_time && lane == 0)
+                    atomicMin((unsigned long long *)&a.tile_time[2 * t],
+                              (unsigned long long)wall_clock64());
+                ++taken;
+                if (lane == 0)
+                    __hip_atomic_store(&a.active[gw], (int32_t)t, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+                r_tile = (int32_t)t;
+            } else {
+                // queue dry: look for a held tile with rows left, 64 entries per step,
+                // starting after this wave's own entry; a full pass of the table
+                // without a find ends the search
+                if (r_scanned >= G || r_miss >= STEAL_MAX_MISSES)
+                    return false;
+                const int32_t j = (int32_t)(((int64_t)gw + 1 + r_scan + lane) % G);
+                const int32_t tj =
+                    __hip_atomic_load(&a.active[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                bool cand = false;
+                if (tj >= 0)
+                    cand = __hip_atomic_load(&a.chunk[tj], __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT) < a.tile_h;
+                const uint64_t cm = ballot(cand);
+                if (cm == 0) {
+                    r_scan = (int32_t)(((int64_t)r_scan + 64) % G);
+                    r_scanned += 64;
+                    continue;
+                }
+                const int32_t first = (int32_t)__builtin_ctzll(cm);
+                r_tile = __builtin_amdgcn_readlane(tj, first);
+                r_scan = (int32_t)(((int64_t)r_scan + first + 1) % G);
+                r_scanned = 0;
+            }
+        }
+    };
 
     // Next work item of this wave, or false when the source is empty.
     auto next_item = [&]() -> bool {
@@ -214,6 +367,8 @@ __global__ void __launch_bounds__(1024) render_kernel(RenderArgs a)
                     if (t >= a.ntiles)
                         return false;
                 } else {
+                    if constexpr (STEAL)
+                        return steal_item();
                     if (q_left == 0) {
                         unsigned long long q = 0;
                         if (lane == 0)
@@ -651,10 +806,11 @@ __global__ void __launch_bounds__(1024) render_kernel(RenderArgs a)
 
 // ---- launch helpers (host) ---------------------------------------------------
 
-template <int POLICY, bool BATCH, bool DEFER, bool PERIODIC>
+template <int POLICY, bool BATCH, bool DEFER, bool PERIODIC, bool STEAL = false>
 static hipError_t launch_one(const RenderArgs &a, dim3 grid, dim3 block, hipStream_t s)
 {
-    hipLaunchKernelGGL((render_kernel<POLICY, BATCH, DEFER, PERIODIC>), grid, block, 0, s, a);
+    hipLaunchKernelGGL((render_kernel<POLICY, BATCH, DEFER, PERIODIC, STEAL>), grid, block, 0, s,
+                       a);
     return hipGetLastError();
 }
 
@@ -662,6 +818,23 @@ template <int POLICY, bool BATCH>
 static hipError_t launch_mode(const RenderArgs &a, int tests, dim3 grid, dim3 block,
                               hipStream_t s)
 {
+    if constexpr (BATCH && (POLICY == POLICY_FCFS_TILES || POLICY == POLICY_ORDERED_TILES)) {
+        if (a.steal) {
+            switch (tests) {
+            case TESTS_EVERY_UPDATE:
+                return launch_one<POLICY, BATCH, false, false, true>(a, grid, block, s);
+            case TESTS_DEFERRED:
+                return launch_one<POLICY, BATCH, true, false, true>(a, grid, block, s);
+            case TESTS_DEFERRED_PERIODIC:
+                return launch_one<POLICY, BATCH, true, true, true>(a, grid, block, s);
+            default:
+                return hipErrorInvalidValue;
+            }
+        }
+    } else {
+        if (a.steal)
+            return hipErrorInvalidValue;
+    }
     switch (tests) {
     case TESTS_EVERY_UPDATE:
         return launch_one<POLICY, BATCH, false, false>(a, grid, block, s);
@@ -711,15 +884,15 @@ hipError_t launch_render(const RenderArgs &a, int policy, bool batch, int tests,
 
 hipError_t launch_clear(unsigned long long *head, int64_t first_slot, int64_t *tile_cost,
                         int32_t *claims, uint64_t *tile_time, int64_t ntiles, uint64_t *stats,
-                        hipStream_t s)
+                        hipStream_t s, int32_t *chunk, int32_t *active, int64_t nwaves)
 {
-    int64_t blocks = (ntiles + 255) / 256;
+    int64_t blocks = ((ntiles > nwaves ? ntiles : nwaves) + 255) / 256;
     if (blocks < 1)
         blocks = 1;
     if (blocks > 4096)
         blocks = 4096;
     hipLaunchKernelGGL(clear_kernel, dim3((unsigned)blocks), dim3(256), 0, s, head, first_slot,
-                       tile_cost, claims, tile_time, ntiles, stats);
+                       tile_cost, claims, tile_time, ntiles, stats, chunk, active, nwaves);
     return hipGetLastError();
 }
 
@@ -731,13 +904,13 @@ int persistent_blocks_per_cu(int policy, bool batch, int tests, int threads)
     do {                                                                                       \
         if (tests == TESTS_EVERY_UPDATE)                                                       \
             e = hipOccupancyMaxActiveBlocksPerMultiprocessor(                                  \
-                &nb, render_kernel<P, B, false, false>, threads, 0);                            \
+                &nb, render_kernel<P, B, false, false, false>, threads, 0);                     \
         else if (tests == TESTS_DEFERRED)                                                      \
             e = hipOccupancyMaxActiveBlocksPerMultiprocessor(                                  \
-                &nb, render_kernel<P, B, true, false>, threads, 0);                             \
+                &nb, render_kernel<P, B, true, false, false>, threads, 0);                      \
         else                                                                                   \
             e = hipOccupancyMaxActiveBlocksPerMultiprocessor(                                  \
-                &nb, render_kernel<P, B, true, true>, threads, 0);                              \
+                &nb, render_kernel<P, B, true, true, false>, threads, 0);                       \
     } while (0)
     if (batch) {
         if (policy == POLICY_ORDERED_TILES)

@@ -77,7 +77,8 @@ class LaunchC(ctypes.Structure):
                 ("tile_cost", ctypes.c_void_p), ("stats", ctypes.c_void_p),
                 ("probe_cap", ctypes.c_int32), ("workers", ctypes.c_int32),
                 ("first_slot", ctypes.c_int64), ("periodicity", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("tile_time", ctypes.c_void_p)]
+                ("reserved", ctypes.c_int32), ("tile_time", ctypes.c_void_p),
+                ("steal", ctypes.c_int32), ("reserved2", ctypes.c_int32)]
 
 
 PLAN_MODES = {"fcfs": 0, "ordered": 1, "probe": 2, "learned": 3, "static": 4, "alternating": 5}
@@ -305,10 +306,11 @@ class Plan:
 
     def launch(self, out, mode="fcfs", use_graph=False, order=None, mlp=None, tile_cost=None,
                stats=None, probe_cap=0, first_slot=0, workers=0, periodicity=0, tile_time=None,
-               stream=None):
+               steal=0, stream=None):
         la = LaunchC(PLAN_MODES[mode] if isinstance(mode, str) else int(mode), int(use_graph),
                      _ptr(order), _ptr(mlp), _ptr(tile_cost), _ptr(stats), int(probe_cap),
-                     int(workers), int(first_slot), int(periodicity), 0, _ptr(tile_time))
+                     int(workers), int(first_slot), int(periodicity), 0, _ptr(tile_time),
+                     int(steal), 0)
         check(lib().mandel_plan_launch(self._h, _ptr(out), ctypes.byref(la), _stream(stream)))
         return out
 

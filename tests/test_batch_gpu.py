@@ -4,6 +4,7 @@
 Counts are compared with the CPU oracle bit for bit (paper Sec. I, Eq. (1)-(2));
 the cost model is compared with the FP64 reference in oracle/mlp.py within
 FP32 tolerances (rtol 1e-3 / atol 1e-5 of the gradient scale)."""
+import ctypes
 import sys
 
 import numpy as np
@@ -169,6 +170,83 @@ def test_plan_tile_timestamps(small_batch):
     with pytest.raises(native.MandelError):
         plan.launch(out, mode="static", workers=4, tile_time=tt)
     plan.close()
+
+
+@pytest.mark.parametrize("tuning", [{}, dict(tile_w=32, tile_h=5, grain=3),
+                                    dict(tile_w=16, tile_h=16, waves_per_group=1, groups=37)])
+def test_plan_row_stealing(small_batch, tuning):
+    # Row stealing hands out the rows of claimed tiles through per-tile counters and
+    # lets waves take rows of tiles others hold once the queue is dry.  The small batch
+    # has far fewer tiles than the grid has waves, so most waves steal.  Every mode,
+    # with periodicity detection, eager and graph replays: images equal the oracle's,
+    # per-tile cost sums, statistics and timestamps are those of the plain queue.
+    views, want = small_batch
+    plan = native.Plan(views, tuning)
+    nt = plan.ntiles
+    tw, th = plan.tuning["tile_w"], plan.tuning["tile_h"]
+    sums = _tile_sums(views, want, tw, th)
+    feat = plan.features()
+    params = torch.tensor(_params(3, feat), dtype=torch.float32, device="cuda")
+    order = torch.tensor(np.random.default_rng(9).permutation(nt), dtype=torch.int32,
+                         device="cuda")
+    cost = torch.zeros(nt, dtype=torch.int64, device="cuda")
+    tt = torch.zeros(2 * nt, dtype=torch.int64, device="cuda")
+    stats = torch.zeros(8, dtype=torch.int64, device="cuda")
+    out = torch.empty((plan.out_size(),), dtype=torch.int32, device="cuda")
+    total = sum(int(w.sum()) for w in want)
+    for mode in ("fcfs", "ordered", "probe", "learned"):
+        kw = dict(order=order) if mode == "ordered" else {}
+        if mode == "learned":
+            kw["mlp"] = params
+        for per in (0, 1):
+            for use_graph in (False, True, True):
+                _log(f"steal {tuning} mode {mode} periodicity {per} graph {use_graph}")
+                out.fill_(-1)
+                cost.fill_(-5)
+                tt.fill_(3)
+                stats.zero_()
+                torch.cuda.synchronize()
+                plan.launch(out, mode=mode, steal=1, periodicity=per, tile_cost=cost,
+                            tile_time=tt, stats=stats, use_graph=use_graph, **kw)
+                torch.cuda.synchronize()
+                _check(plan, out, want)
+                assert np.array_equal(cost.cpu().numpy(), sums)
+                st = stats.cpu().numpy()
+                assert st[1] == total and st[3] == nt
+                t = tt.cpu().numpy().view(np.uint64).reshape(nt, 2)
+                assert (t[:, 0] <= t[:, 1]).all() and (t[:, 1] > 3).all()
+    # a queue that starts at slot k: tiles before it are neither rendered nor stolen
+    for k in (1, nt // 2, nt - 1, nt, nt + 3):
+        _log(f"steal {tuning} first_slot {k}")
+        out.fill_(-1)
+        cost.fill_(-5)
+        stats.zero_()
+        plan.launch(out, steal=1, first_slot=k, tile_cost=cost, stats=stats)
+        torch.cuda.synchronize()
+        c = cost.cpu().numpy()
+        assert (c[:k] == 0).all() and np.array_equal(c[k:], sums[k:])
+        o = out.cpu().numpy()
+        assert int(o[o >= 0].sum()) == int(sums[k:].sum())
+        assert stats.cpu().numpy()[3] == max(nt - k, 0)
+    plan.close()
+
+
+def test_plan_row_stealing_rejections(small_batch):
+    views, _ = small_batch
+    plan = native.Plan(views)
+    out = torch.empty((plan.out_size(),), dtype=torch.int32, device="cuda")
+    for bad in (dict(steal=2), dict(steal=-1), dict(steal=1, mode="static", workers=4),
+                dict(steal=1, mode="alternating", workers=4)):
+        with pytest.raises(native.MandelError):
+            plan.launch(out, **bad)
+    la = native.LaunchC(0, 0, None, None, None, None, 0, 0, 0, 0, 0, None, 0, 1)
+    assert native.lib().mandel_plan_launch(plan._h, native._ptr(out), ctypes.byref(la),
+                                           None) == native.EINVAL
+    plan.close()
+    parts = native.Plan(views, dict(tile_parts=4))
+    with pytest.raises(native.MandelError):
+        parts.launch(out, steal=1)
+    parts.close()
 
 
 def test_single_view_plan_equals_render():
