@@ -380,6 +380,64 @@ def makespans(torch, native, workloads, costmodel, reps: int, clock_khz: float,
     return res
 
 
+def stress_batch(torch, native, workloads, costmodel, reps: int, clock_khz: float, params,
+                 cus: int, contiguous_rows: bool = False) -> dict:
+    """Stress batch in one plan (64x8 tiles): a 16384 x 16384 deep zoom of width 1e-12 at a
+    boundary point (max_iter 50000) submitted first, then 4096 views of 512 x 512 drawn
+    like the uneven batch.  Queue orders FCFS (submission order), probe, learned and true
+    cost, and the paper's alternating row partition over the concatenated rows (every
+    worker resident); the contiguous partition only on request (about a minute per
+    launch: the deep view's rows fall to a few workers).  Every order must give the
+    FCFS counts."""
+    views = workloads.c5()
+    plan = native.Plan(views)
+    log(f"stress: {len(views)} views, {plan.npixels} px, {plan.ntiles} tiles")
+    out = torch.empty(plan.out_size(), dtype=torch.int32, device="cuda")
+    cost = torch.empty(plan.ntiles, dtype=torch.int64, device="cuda")
+    stats = torch.zeros(8, dtype=torch.int64, device="cuda")
+    plan.launch(out, tile_cost=cost)
+    torch.cuda.synchronize()
+    sum_counts = int(cost.sum().item())
+    ref = out.clone()
+    # tiles are numbered view by view, the deep view first
+    nt0 = native.tile_count(views[0].m, views[0].n, plan.tuning["tile_w"], plan.tuning["tile_h"])
+    res = {"views": len(views), "pixels": plan.npixels, "tiles": plan.ntiles,
+           "sum_counts": sum_counts, "deep_view_sum_counts": int(cost[:nt0].sum().item())}
+    if params is not None:
+        res["cost_model_eval"] = costmodel.evaluate(params, plan.features(),
+                                                    native.cost_targets(cost))
+    true_perm = native.order_desc(native.cost_targets(cost))
+    runs = [("fcfs", "fcfs", {}), ("probe_lpt", "probe", {}),
+            ("true_cost_lpt", "ordered", {"order": true_perm})]
+    if params is not None:
+        runs.insert(2, ("learned_lpt", "learned", {"mlp": params}))
+    W = cus * 7
+    if contiguous_rows:
+        runs.append(("static_rows_concatenated", "static", {"workers": W}))
+    runs.append(("alternating_rows_concatenated", "alternating", {"workers": W}))
+    ms = {}
+    for name, mode, kw in runs:
+        out.fill_(-1)
+        t = timed_ms(torch, lambda: plan.launch(out, mode=mode, use_graph=True, **kw), reps,
+                     f"stress {name}")
+        assert torch.equal(out, ref), f"stress {name} changed the counts"
+        stats.zero_()
+        plan.launch(out, mode=mode, stats=stats, **kw)
+        torch.cuda.synchronize()
+        st = [int(v) for v in stats.cpu().tolist()]
+        ms[name] = {"ms": t, "pixel_iterations_per_s": sum_counts / (t / 1e3),
+                    "tail": tail_fraction(st, clock_khz)}
+    res["makespan_ms"] = ms
+    res["row_workers"] = W
+    best_rows = min(ms[k]["ms"] for k in ("static_rows_concatenated",
+                                          "alternating_rows_concatenated") if k in ms)
+    for name in ("fcfs", "learned_lpt", "true_cost_lpt"):
+        if name in ms:
+            res[f"speedup_{name}_vs_best_row_partition"] = best_rows / ms[name]["ms"]
+    plan.close()
+    return res
+
+
 def comparisons(torch, native, view, plan, out, cost, sum_counts, stream) -> dict:
     """The plain mandel_render (FCFS in tile order) and the true-cost order on the
     headline view, and the cost of the probe features alone."""
@@ -454,6 +512,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-makespan", action="store_true")
     ap.add_argument("--makespan-reps", type=int, default=3)
+    ap.add_argument("--no-stress", action="store_true",
+                    help="skip the stress batch (16384^2 deep zoom + 4096 views of 512^2)")
+    ap.add_argument("--stress-contiguous-rows", action="store_true",
+                    help="also time the contiguous row partition on the stress batch (~1 min "
+                         "per launch)")
     ap.add_argument("--cpu-rows-step", type=int, default=4)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 1 GiB device-to-device copy (counter calibration)")
@@ -478,7 +541,7 @@ def main():
     clock_khz = float(dinfo["wall_clock_khz"]) or 100000.0
     stream = torch.cuda.current_stream()
     if args.profile:
-        args.no_makespan = args.no_cpu_baseline = True
+        args.no_makespan = args.no_cpu_baseline = args.no_stress = True
         params, cm_info, mode = None, {}, "probe"
     else:
         log("bench: training the cost model")
@@ -662,6 +725,10 @@ def main():
     if not args.no_makespan:
         res["makespan"] = makespans(torch, native, workloads, costmodel, args.makespan_reps,
                                     clock_khz, params, int(dinfo["compute_units"]))
+    if not args.no_stress:
+        res["stress_batch"] = stress_batch(torch, native, workloads, costmodel, 1, clock_khz,
+                                           params, int(dinfo["compute_units"]),
+                                           contiguous_rows=args.stress_contiguous_rows)
     if not args.no_cpu_baseline:
         threads = min(16, os.cpu_count() or 1)
         log(f"bench: cpu baseline on {threads} threads")
