@@ -328,6 +328,13 @@ typedef struct mandel_launch {
  * int32, each view at its out_offset) on `stream`.  All kernels of a launch
  * go to that stream in order.  A plan has one queue: launches of the same
  * plan must not overlap in time (same stream, or synchronise between them).
+ * Different plans share nothing and may run concurrently on different streams.
+ * The first launch in PROBE_LPT or LEARNED_LPT mode allocates the plan's order
+ * buffers (features, keys, permutation: 280 bytes per tile, and a 32 KiB histogram),
+ * and the first launch with steal = 1 its row counters and held-tile table
+ * (4 bytes per tile and per wavefront), with hipMalloc (synchronous; -2 ENOMEM
+ * on failure); they live until mandel_plan_destroy.  Returns 0, or -1 EINVAL /
+ * -2 ENOMEM / -3 EHIP with nothing enqueued.
  */
 int mandel_plan_launch(mandel_plan *plan, int32_t *out_base, const mandel_launch *args,
                        void *stream);

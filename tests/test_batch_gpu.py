@@ -379,3 +379,30 @@ def test_fp64_probe_runs():
     for kind in (0, 1, 2):
         r = native.fp64_probe(kind, iters=200, blocks_per_cu=2)
         assert r["ms"] > 0 and r["flops"] > 0 and r["tflops"] < 200
+
+
+def test_two_plans_on_two_streams_concurrently(small_batch):
+    # Consecutive steps alternate between two plans (each with its own queue head,
+    # features, order and graph) on two streams with no synchronisation between them,
+    # so their launches overlap on the device: every step's image must still be the
+    # oracle's, in every queue mode and with graph replays.
+    views, want = small_batch
+    plans = [native.Plan(views), native.Plan(views)]
+    params = torch.tensor(_params(3, plans[0].features()), dtype=torch.float32, device="cuda")
+    streams = [torch.cuda.current_stream(), torch.cuda.Stream()]
+    outs = [torch.full((plans[0].out_size(),), -1, dtype=torch.int32, device="cuda")
+            for _ in range(2)]
+    torch.cuda.synchronize()
+    for mode, kw in (("fcfs", {}), ("probe", {}), ("learned", dict(mlp=params))):
+        for o in outs:
+            o.fill_(-1)
+        torch.cuda.synchronize()
+        _log(f"two streams, mode {mode}")
+        for k in range(6):
+            i = k % 2
+            plans[i].launch(outs[i], mode=mode, use_graph=True, stream=streams[i], **kw)
+        torch.cuda.synchronize()
+        for i in range(2):
+            _check(plans[i], outs[i], want)
+    for p in plans:
+        p.close()
