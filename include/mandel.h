@@ -163,7 +163,9 @@ typedef struct mandel_sched {
     int32_t block_iters;     /* longest deferred-test block K, 1..65536 [1024] */
     int32_t young_iters;     /* pixels younger than this are tested every update [4] */
     int32_t refill_lanes;    /* while updates are tested one by one, lanes whose pixel
-                                finished are refilled once this many are idle, 1..64 [16] */
+                                finished are refilled once this many are idle; when a
+                                block of untested updates ends, once min(this, 8) are
+                                idle (or none is active); 1..64 [16] */
     const int32_t *order;    /* device int32[ntiles], ORDERED_TILES only: a permutation */
     int64_t *tile_cost;      /* device int64[ntiles] or NULL: sum of counts per tile
                                 (tile policies; cleared by the call) */
