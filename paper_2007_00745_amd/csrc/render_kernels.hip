@@ -11,7 +11,12 @@
 //   * lanes whose pixel finished take the next pixels of the wave's current
 //     item (ballot + mbcnt compaction), and the wave claims the next item as
 //     soon as the current one has no pixels left, so lanes idle only briefly
-//     (until a refill round) and in the last items of the whole launch;
+//     (until a refill round) and in the last items of the whole launch.  A
+//     refill round starts once refill_lanes lanes are idle while updates are
+//     tested one by one, or min(refill_lanes, 8) when a block of untested
+//     updates ends, so refills of finished pixels come in groups;
+//   * optionally (a separate instantiation), the rows of tiles other waves
+//     hold are shared out once the queue is dry (row stealing);
 //   * the |z|^2 > R^2 test may be deferred over blocks of K updates for
 //     pixels where an escape provably cannot be undone (R >= 2 and
 //     |c| <= (R^2 - R)(1 - 2^-20): after the first escape |z| keeps growing,
