@@ -164,3 +164,41 @@ def test_bench_configuration_batch(quick_model):
     assert int(out.min().item()) >= 1
     _sample_check(plan, out, np.random.default_rng(745), per_view=48)
     plan.close()
+
+
+def _list_schedule(costs, order, workers):
+    # Graham's list scheduling: each tile, in queue order, goes to the worker that
+    # becomes free first; the makespan is the time the last worker finishes.
+    import heapq
+    free = [0] * workers
+    for t in order:
+        w = heapq.heappop(free)
+        heapq.heappush(free, w + int(costs[t]))
+    return max(free)
+
+
+def test_learned_order_list_schedule_gain(quick_model):
+    # What the trained network gains over FCFS on the 8192^2 view, without timing noise:
+    # the logged per-tile costs list-scheduled on the device's resident wavefronts in
+    # FCFS (tile) order, in the learned order and in the true-cost order.  Every
+    # makespan respects the list-scheduling lower bound max(sum / W, max tile); the
+    # learned order must beat FCFS, whose expensive middle tiles come last.
+    v = workloads.c2(8192, 10000)
+    plan = native.Plan([v])
+    out = torch.empty(plan.out_size(), dtype=torch.int32, device="cuda")
+    cost = torch.empty(plan.ntiles, dtype=torch.int64, device="cuda")
+    plan.launch(out, tile_cost=cost)
+    keys = native.mlp_forward(quick_model, plan.features())
+    learned = native.order_desc(keys).cpu().numpy()
+    torch.cuda.synchronize()
+    c = cost.cpu().numpy()
+    W = int(native.device_info()["compute_units"]) * 28
+    true = np.argsort(-c, kind="stable")
+    ms = {name: _list_schedule(c, order, W) for name, order in
+          (("fcfs", np.arange(plan.ntiles)), ("learned", learned), ("true_cost", true))}
+    bound = max(-(-int(c.sum()) // W), int(c.max()))
+    _log(f"list-schedule makespans (iterations per wave, W={W}): {ms}, lower bound {bound}")
+    assert sorted(learned.tolist()) == list(range(plan.ntiles))
+    assert all(m >= bound for m in ms.values())
+    assert ms["learned"] < ms["fcfs"]
+    plan.close()
