@@ -1,0 +1,117 @@
+"""Randomised parity over the configuration space (seeded, so every run checks the
+same cases): each case draws a small batch of views (full window, boundary zooms
+down to pitch 1e-9, random regions, the all-escaping outside; ragged and empty
+sizes; max_iter 1..3000; R from 1.5 to 400), a random plan tuning (tile shape,
+claim grain, wavefronts per group, deferred block length, young updates, refill
+lanes, row parts, group count) and two random launches of the same plan (FCFS,
+ordered over a random permutation, probe, learned with random weights, the
+paper's static and alternating rows over the concatenated rows; periodicity
+detection, row stealing, eager or from the graph).  Every image must equal the
+oracle's bit for bit (Sec. I, Eq. (1)-(2): the schedule never changes a count),
+the statistics' count sum must equal the oracle's, and in the queue modes so must
+the per-tile cost log's total."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import mlp as mlp_ref
+from paper_2007_00745_amd import native, workloads
+
+pytestmark = pytest.mark.gpu
+
+# points on or near the boundary of the set (seahorse and elephant valleys, the
+# period-3 bulb's neck, an antenna point, the cardioid's cusp)
+NEAR_BOUNDARY = [(-0.7436438870371587, 0.1318259042053119), (0.2850, 0.0110),
+                 (-0.1592, 1.0317), (-1.7490, 0.0), (0.25, 0.0), (-0.75, 0.1)]
+
+
+def _log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def _view(rng):
+    m = int(rng.choice([0, 1, 3]) if rng.random() < 0.08 else rng.integers(1, 150))
+    n = int(rng.choice([0, 1, 5]) if rng.random() < 0.08 else rng.integers(1, 200))
+    kind = int(rng.integers(0, 4))
+    if kind == 0 and m > 0 and n > 0:
+        win = workloads.window_from_bounds(-2.0, 1.0, -1.2, 1.2, m, n)
+    elif kind == 1:
+        cx, cy = NEAR_BOUNDARY[int(rng.integers(0, len(NEAR_BOUNDARY)))]
+        d = 10.0 ** rng.uniform(-9, -3)
+        win = (cx, cy, d, d * rng.uniform(0.5, 2.0))
+    elif kind == 2:
+        d = 10.0 ** rng.uniform(-4, -1.5)
+        win = (rng.uniform(-2.2, 0.8), rng.uniform(-1.3, 1.3), d, d)
+    else:
+        d = 10.0 ** rng.uniform(-3, -1)
+        win = (rng.choice([-2.6, 2.3]), rng.uniform(-1.0, 1.0), d, d)
+    max_iter = int(np.exp(rng.uniform(0.0, np.log(3000.0))))
+    R = float(rng.choice([2.0, 2.0, 2.0, 1.5, 4.0, 400.0]))
+    return workloads.View(tuple(float(x) for x in win), m, n, max_iter, R)
+
+
+def _tuning(rng):
+    return dict(tile_w=int(rng.choice([8, 16, 32, 64, 128])),
+                tile_h=int(rng.choice([1, 2, 4, 8, 16])),
+                grain=int(rng.choice([1, 1, 2, 3, 8])),
+                waves_per_group=int(rng.choice([1, 2, 4, 8])),
+                block_iters=int(rng.choice([1, 8, 64, 1024])),
+                young_iters=int(rng.choice([1, 4, 16])),
+                refill_lanes=int(rng.choice([1, 8, 16, 64])),
+                tile_parts=int(rng.choice([1, 1, 2, 4])),
+                groups=int(rng.choice([0, 0, 37, 300])))
+
+
+def _launch_kw(rng, plan, params):
+    mode = str(rng.choice(["fcfs", "ordered", "probe", "learned", "static", "alternating"]))
+    kw = dict(mode=mode, use_graph=bool(rng.random() < 0.5),
+              periodicity=int(rng.random() < 0.3))
+    if mode == "ordered":
+        kw["order"] = torch.tensor(rng.permutation(plan.ntiles), dtype=torch.int32,
+                                   device="cuda")
+    elif mode == "learned":
+        kw["mlp"] = params
+    elif mode in ("static", "alternating"):
+        kw["workers"] = int(rng.choice([1, 7, 64, 500]))
+    if mode not in ("static", "alternating") and plan.tuning["tile_parts"] == 1:
+        kw["steal"] = int(rng.random() < 0.3)
+    return kw
+
+
+@pytest.mark.parametrize("seed", range(160))
+def test_random_batch_and_schedule(seed):
+    rng = np.random.default_rng(9000 + seed)
+    views = [_view(rng) for _ in range(int(rng.integers(1, 5)))]
+    want = [oracle.render(v.window, v.m, v.n, v.max_iter, v.R) for v in views]
+    total = sum(int(w.sum(dtype=np.int64)) for w in want)
+    tun = _tuning(rng)
+    plan = native.Plan(views, tun)
+    p = mlp_ref.init_params(rng, mu=rng.normal(size=68) * 0.1, sd=rng.uniform(0.5, 2.0, 68))
+    params = torch.tensor(p, dtype=torch.float32, device="cuda")
+    out = torch.empty((max(plan.out_size(), 1),), dtype=torch.int32, device="cuda")
+    stats = torch.zeros(8, dtype=torch.int64, device="cuda")
+    cost = torch.empty((max(plan.ntiles, 1),), dtype=torch.int64, device="cuda")
+    for rep in range(2):
+        kw = _launch_kw(rng, plan, params)
+        rows = kw["mode"] in ("static", "alternating")
+        desc = {k: v for k, v in kw.items() if k not in ("order", "mlp")}
+        _log(f"seed {seed} rep {rep}: {len(views)} views "
+             f"{[(v.m, v.n, v.max_iter, v.R) for v in views]} tuning {tun} launch {desc}")
+        out.fill_(-1)
+        stats.zero_()
+        if not rows:
+            kw["tile_cost"] = cost
+        torch.cuda.synchronize()
+        plan.launch(out, stats=stats, **kw)
+        torch.cuda.synchronize()
+        imgs = plan.view_images(out.cpu())
+        for k, (g, w) in enumerate(zip(imgs, want)):
+            assert np.array_equal(g.numpy(), w), f"seed {seed} rep {rep} view {k}"
+        if plan.ntiles > 0:
+            assert int(stats.cpu()[1]) == total
+            if not rows:
+                assert int(cost[:plan.ntiles].sum().item()) == total
+    plan.close()
