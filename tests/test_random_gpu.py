@@ -115,3 +115,87 @@ def test_random_batch_and_schedule(seed):
             if not rows:
                 assert int(cost[:plan.ntiles].sum().item()) == total
     plan.close()
+
+
+@pytest.mark.parametrize("seed", range(120))
+def test_random_single_view_schedule(seed):
+    # mandel_render_sched with a random schedule of every policy (the queue, a random
+    # permutation, the paper's static and alternating rows, the grid launch), random
+    # test mode, block length, young updates, refill lanes, row parts and claim grain:
+    # the image equals the oracle's; the claim log says every tile part was claimed
+    # once (tile policies) or every row was taken by the worker the paper assigns
+    # (Sec. III-A, III-C); the statistics' count sum equals the oracle's.
+    from oracle import partition
+    rng = np.random.default_rng(12000 + seed)
+    v = _view(rng)
+    want = oracle.render(v.window, v.m, v.n, v.max_iter, v.R)
+    policy = str(rng.choice(["fcfs", "ordered", "static", "alternating", "grid"]))
+    tw = int(rng.choice([8, 16, 32, 64, 128]))
+    th = int(rng.choice([1, 2, 4, 8, 16]))
+    check_every = int(rng.random() < 0.3)
+    kw = dict(policy=policy, tile_w=tw, tile_h=th, check_every=check_every,
+              periodicity=int(check_every == 0 and rng.random() < 0.3),
+              waves_per_group=int(rng.choice([1, 2, 4, 8])),
+              block_iters=int(rng.choice([1, 8, 64, 1024])),
+              young_iters=int(rng.choice([1, 4, 16])),
+              refill_lanes=int(rng.choice([1, 8, 16, 64])))
+    rows = policy in ("static", "alternating")
+    nt = native.tile_count(v.m, v.n, tw, th)
+    parts = 1
+    if policy in ("fcfs", "ordered"):
+        parts = int(rng.choice([1, 1, 2, 4]))
+        kw.update(tile_parts=parts, grain=int(rng.choice([1, 2, 3, 8])))
+    if policy == "ordered":
+        kw["order"] = torch.tensor(rng.permutation(max(nt, 1)), dtype=torch.int32, device="cuda")
+    W = 0
+    if rows:
+        W = int(rng.choice([1, 3, 64, 1000]))
+        kw["workers"] = W
+    elif policy != "grid" and rng.random() < 0.3:
+        kw["workers"] = int(rng.choice([1, 37, 300]))
+    nlog = v.m if rows else nt
+    claims = torch.full((max(nlog, 1),), 99, dtype=torch.int32, device="cuda")
+    stats = torch.zeros(8, dtype=torch.int64, device="cuda")
+    desc = {k: x for k, x in kw.items() if k != "order"}
+    _log(f"seed {seed}: view {(v.m, v.n, v.max_iter, v.R)} window {v.window} sched {desc}")
+    got = native.render_sched(v.window, v.m, v.n, v.max_iter, v.R, claims=claims, stats=stats,
+                              **kw)
+    torch.cuda.synchronize()
+    assert np.array_equal(got.cpu().numpy(), want), f"seed {seed}"
+    if v.m == 0 or v.n == 0:
+        return
+    assert int(stats.cpu()[1]) == int(want.sum(dtype=np.int64))
+    log = claims.cpu().numpy()[:nlog]
+    if rows:
+        fn = partition.naive_rows if policy == "static" else partition.alternating_rows
+        owner = np.zeros(v.m, dtype=np.int64)
+        for r in range(W):
+            owner[fn(v.m, W, r)] = r + 1
+        assert np.array_equal(log, owner)
+    else:
+        hs = np.minimum(th, v.m - np.arange(0, v.m, th))
+        per = np.array([sum(1 for p in range(parts) if ((p + 1) * h) // parts > (p * h) // parts)
+                        for h in hs])
+        assert np.array_equal(log.reshape(len(hs), -1),
+                              np.repeat(per[:, None], -(-v.n // tw), axis=1))
+
+
+@pytest.mark.parametrize("seed", range(24))
+def test_random_double_double(seed):
+    # mandel_render_dd on random deep windows (pitch 1e-19 .. 1e-12 at points near the
+    # boundary, centre low parts drawn at the scale of an ulp of the high parts,
+    # ragged sizes, max_iter up to 2000) equals the double-double oracle bit for bit.
+    import oracle.dd as dd
+    rng = np.random.default_rng(15000 + seed)
+    cx, cy = NEAR_BOUNDARY[int(rng.integers(0, len(NEAR_BOUNDARY)))]
+    d = 10.0 ** rng.uniform(-19, -12)
+    win = (cx, float(rng.uniform(-1, 1) * 1e-17 * max(abs(cx), 1e-3)),
+           cy, float(rng.uniform(-1, 1) * 1e-17 * max(abs(cy), 1e-3)), d, d * rng.uniform(0.5, 2))
+    m, n = int(rng.integers(1, 40)), int(rng.integers(1, 70))
+    max_iter = int(np.exp(rng.uniform(0.0, np.log(2000.0))))
+    R = float(rng.choice([2.0, 2.0, 4.0]))
+    _log(f"seed {seed}: dd window {win} size {m}x{n} max_iter {max_iter} R {R}")
+    want = dd.render(win, m, n, max_iter, R)
+    got = native.render_dd(win, m, n, max_iter, R)
+    torch.cuda.synchronize()
+    assert np.array_equal(got.cpu().numpy(), want), f"seed {seed}"
