@@ -324,3 +324,37 @@ def test_c2_full_size_sampled():
     idx = np.concatenate(idx)
     want = oracle.render_pixels(v.window, v.m, v.n, v.max_iter, v.R, idx, threads=16)
     assert np.array_equal(got.ravel()[idx], want)
+
+
+def test_beyond_2_31_pixels():
+    # Output indices past 2^31: one 46341 x 46341 view (2 147 488 281 pixels, 8.6 GB of
+    # counts) followed in the same plan by a small view whose offset lies beyond 2^31,
+    # and the same large view through mandel_render.  Sampled pixels (around index 2^31,
+    # the corners, random ones) and the whole small view equal the oracle; the large
+    # image is symmetric under conjugation (its window is centred on the real axis).
+    side = 46341
+    big = workloads.View(workloads.window_from_bounds(-2.0, 1.0, -1.2, 1.2, side, side), side,
+                         side, 12)
+    small = workloads.View(workloads.window_from_bounds(-1.0, 0.5, -0.6, 0.6, 33, 70), 33, 70, 300)
+    plan = native.Plan([big, small])
+    assert plan.out_offsets[1] == big.pixels and big.pixels > 2 ** 31
+    out = torch.full((plan.out_size(),), -1, dtype=torch.int32, device="cuda")
+    plan.launch(out)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(31)
+    edge = np.array([0, side - 1, (side - 1) * side, side * side - 1,
+                     2 ** 31 - 1, 2 ** 31, 2 ** 31 + 1], dtype=np.int64)
+    idx = np.concatenate([edge, rng.integers(2 ** 31 - 5000, big.pixels, 500),
+                          rng.integers(0, big.pixels, 2000)])
+    want = oracle.render_pixels(big.window, side, side, big.max_iter, big.R, idx, threads=16)
+    got = out[torch.tensor(idx, device="cuda")].cpu().numpy()
+    assert np.array_equal(got, want)
+    img = out[:big.pixels].view(side, side)
+    assert torch.equal(img, torch.flip(img, dims=[0]))
+    w_small = oracle.render(small.window, small.m, small.n, small.max_iter, small.R)
+    assert np.array_equal(out[big.pixels:].view(small.m, small.n).cpu().numpy(), w_small)
+    plan.close()
+    del img
+    out2 = native.render(big.window, side, side, big.max_iter, big.R)
+    torch.cuda.synchronize()
+    assert torch.equal(out2.view(-1), out[:big.pixels])
