@@ -173,6 +173,41 @@ def _ptr(t) -> int:
     return t.data_ptr()
 
 
+def _dev(t, dtype, numel: int, name: str):
+    """Device pointer of an optional buffer (None -> NULL) after checking what the
+    library will read or write through it: element type, contiguity, at least
+    `numel` elements, GPU memory.  A wrong buffer raises here instead of reaching
+    a kernel."""
+    if t is None:
+        return None
+    dts = dtype if isinstance(dtype, tuple) else (dtype,)
+    if t.dtype not in dts:
+        raise ValueError(f"{name} must be {' or '.join(str(d) for d in dts)}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.numel() < numel:
+        raise ValueError(f"{name} has {t.numel()} elements, needs at least {numel}")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a GPU tensor")
+    return t.data_ptr()
+
+
+def _i64():
+    import torch
+    u64 = getattr(torch, "uint64", None)
+    return (torch.int64,) if u64 is None else (torch.int64, u64)
+
+
+def _f32():
+    import torch
+    return torch.float32
+
+
+def _i32():
+    import torch
+    return torch.int32
+
+
 def _stream(stream) -> int:
     import torch
     if stream is None:
@@ -212,8 +247,9 @@ def render_dd(window, m: int, n: int, max_iter: int, R: float, out=None, stats=N
     cy0_hi, cy0_lo, dx, dy).  Returns the (m, n) int32 tensor."""
     out = _out(out, m, n)
     w = WindowDD(*[float(v) for v in window])
+    st = _dev(stats, _i64(), 4, "stats")
     check(lib().mandel_render_dd(ctypes.byref(w), m, n, int(max_iter), float(R), _ptr(out),
-                                 _ptr(stats), _stream(stream)))
+                                 st, _stream(stream)))
     return out
 
 
@@ -223,8 +259,10 @@ def colour_boolean(counts, max_iter: int, rgb=None, stream=None):
     import torch
     if rgb is None:
         rgb = torch.empty(tuple(counts.shape) + (3,), dtype=torch.uint8, device=counts.device)
-    check(lib().mandel_colour_boolean(_ptr(counts), counts.numel(), int(max_iter), _ptr(rgb),
-                                      _stream(stream)))
+    npix = counts.numel()
+    cp = _dev(counts, torch.int32, npix, "counts")
+    rp = _dev(rgb, torch.uint8, 3 * npix, "rgb")
+    check(lib().mandel_colour_boolean(cp, npix, int(max_iter), rp, _stream(stream)))
     return rgb
 
 
@@ -239,6 +277,7 @@ def make_sched(policy="fcfs", tile_w=0, tile_h=0, grain=0, workers=0, waves_per_
                check_every=0, block_iters=0, young_iters=0, refill_lanes=0, order=None,
                tile_cost=None, claims=None, stats=None, tile_parts=0, first_slot=0,
                periodicity=0, tile_time=None) -> Sched:
+    """The mandel_sched struct as given (pointers unchecked: render_sched checks them)."""
     pol = POLICIES[policy] if isinstance(policy, str) else int(policy)
     return Sched(pol, tile_w, tile_h, grain, workers, waves_per_group, check_every,
                  block_iters, young_iters, refill_lanes, _ptr(order), _ptr(tile_cost),
@@ -248,8 +287,20 @@ def make_sched(policy="fcfs", tile_w=0, tile_h=0, grain=0, workers=0, waves_per_
 
 def render_sched(window, m: int, n: int, max_iter: int, R: float, out=None, stream=None,
                  **sched):
-    """mandel_render_sched with the schedule fields of mandel_sched as keywords."""
+    """mandel_render_sched with the schedule fields of mandel_sched as keywords.  The
+    optional buffers are checked against the sizes this call implies."""
     out = _out(out, m, n)
+    pol = sched.get("policy", "fcfs")
+    pol = POLICIES[pol] if isinstance(pol, str) else int(pol)
+    rows = pol in (STATIC_ROWS, ALTERNATING_ROWS)
+    nt = 0
+    if m > 0 and n > 0 and not rows:
+        nt = max(tile_count(m, n, sched.get("tile_w") or 64, sched.get("tile_h") or 8), 0)
+    for key, dt, size in (("order", _i32(), nt), ("tile_cost", _i64(), nt),
+                          ("claims", _i32(), m if rows else nt), ("stats", _i64(), 8),
+                          ("tile_time", _i64(), 2 * nt)):
+        if sched.get(key) is not None:
+            _dev(sched[key], dt, size, key)
     s = make_sched(**sched)
     w = Window(*[float(v) for v in window])
     check(lib().mandel_render_sched(ctypes.byref(w), m, n, int(max_iter), float(R), _ptr(out),
@@ -307,18 +358,22 @@ class Plan:
     def launch(self, out, mode="fcfs", use_graph=False, order=None, mlp=None, tile_cost=None,
                stats=None, probe_cap=0, first_slot=0, workers=0, periodicity=0, tile_time=None,
                steal=0, stream=None):
+        nt = self.ntiles
         la = LaunchC(PLAN_MODES[mode] if isinstance(mode, str) else int(mode), int(use_graph),
-                     _ptr(order), _ptr(mlp), _ptr(tile_cost), _ptr(stats), int(probe_cap),
-                     int(workers), int(first_slot), int(periodicity), 0, _ptr(tile_time),
-                     int(steal), 0)
-        check(lib().mandel_plan_launch(self._h, _ptr(out), ctypes.byref(la), _stream(stream)))
+                     _dev(order, _i32(), nt, "order"), _dev(mlp, _f32(), MLP_PARAMS, "mlp"),
+                     _dev(tile_cost, _i64(), nt, "tile_cost"), _dev(stats, _i64(), 8, "stats"),
+                     int(probe_cap), int(workers), int(first_slot), int(periodicity), 0,
+                     _dev(tile_time, _i64(), 2 * nt, "tile_time"), int(steal), 0)
+        op = _dev(out, _i32(), self.out_size(), "out")
+        check(lib().mandel_plan_launch(self._h, op, ctypes.byref(la), _stream(stream)))
         return out
 
     def features(self, feat=None, probe_cap: int = 0, stream=None):
         import torch
         if feat is None:
             feat = torch.empty((self.ntiles, NFEAT), dtype=torch.float32, device="cuda")
-        check(lib().mandel_plan_features(self._h, _ptr(feat), int(probe_cap), _stream(stream)))
+        fp = _dev(feat, torch.float32, self.ntiles * NFEAT, "feat")
+        check(lib().mandel_plan_features(self._h, fp, int(probe_cap), _stream(stream)))
         return feat
 
     def view_images(self, out):
@@ -344,7 +399,9 @@ def mlp_forward(params, x, y=None, stream=None):
     n = x.shape[0]
     if y is None:
         y = torch.empty(n, dtype=torch.float32, device=x.device)
-    check(lib().mandel_mlp_forward(_ptr(params), _ptr(x), n, _ptr(y), _stream(stream)))
+    check(lib().mandel_mlp_forward(_dev(params, torch.float32, MLP_PARAMS, "params"),
+                                   _dev(x, torch.float32, n * NFEAT, "x"),
+                                   n, _dev(y, torch.float32, n, "y"), _stream(stream)))
     return y
 
 
@@ -358,9 +415,14 @@ def mlp_train_step(params, m, v, t: int, x, target, idx, lr: float, loss=None, w
     B = idx.numel()
     if work is None:
         work = torch.empty(mlp_work_floats(B), dtype=torch.float32, device=x.device)
-    check(lib().mandel_mlp_train_step(_ptr(params), _ptr(m), _ptr(v), int(t), _ptr(x),
-                                      _ptr(target), _ptr(idx), B, float(lr), _ptr(loss),
-                                      _ptr(work), _stream(stream)))
+    f32 = torch.float32
+    nx = x.shape[0]
+    check(lib().mandel_mlp_train_step(
+        _dev(params, f32, MLP_PARAMS, "params"), _dev(m, f32, MLP_PARAMS, "adam_m"),
+        _dev(v, f32, MLP_PARAMS, "adam_v"), int(t), _dev(x, f32, nx * NFEAT, "x"),
+        _dev(target, f32, nx, "target"), _dev(idx, torch.int32, B, "idx"), B, float(lr),
+        _dev(loss, f32, 1, "loss"), _dev(work, f32, mlp_work_floats(B), "work"),
+        _stream(stream)))
     return work
 
 
@@ -369,20 +431,27 @@ def order_desc(keys, perm=None, stream=None):
     n = keys.numel()
     if perm is None:
         perm = torch.empty(n, dtype=torch.int32, device=keys.device)
-    check(lib().mandel_order_desc(_ptr(keys), n, _ptr(perm), _stream(stream)))
+    check(lib().mandel_order_desc(_dev(keys, torch.float32, n, "keys"), n,
+                                  _dev(perm, torch.int32, n, "perm"), _stream(stream)))
     return perm
 
 
 def mlp_set_norm(params, feat, stream=None):
-    check(lib().mandel_mlp_set_norm(_ptr(params), _ptr(feat), feat.shape[0], _stream(stream)))
+    import torch
+    n = feat.shape[0]
+    check(lib().mandel_mlp_set_norm(_dev(params, torch.float32, MLP_PARAMS, "params"),
+                                    _dev(feat, torch.float32, n * NFEAT, "feat"), n,
+                                    _stream(stream)))
     return params
 
 
 def cost_targets(cost, target=None, stream=None):
     import torch
+    n = cost.numel()
     if target is None:
-        target = torch.empty(cost.numel(), dtype=torch.float32, device=cost.device)
-    check(lib().mandel_cost_targets(_ptr(cost), cost.numel(), _ptr(target), _stream(stream)))
+        target = torch.empty(n, dtype=torch.float32, device=cost.device)
+    check(lib().mandel_cost_targets(_dev(cost, _i64(), n, "cost"), n,
+                                    _dev(target, torch.float32, n, "target"), _stream(stream)))
     return target
 
 

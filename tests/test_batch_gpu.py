@@ -406,3 +406,31 @@ def test_two_plans_on_two_streams_concurrently(small_batch):
             _check(plans[i], outs[i], want)
     for p in plans:
         p.close()
+
+
+def test_binding_rejects_wrong_buffers(small_batch):
+    # wrong element types or sizes raise in the binding; nothing is launched
+    views, want = small_batch
+    plan = native.Plan(views)
+    nt = plan.ntiles
+    out = torch.full((plan.out_size(),), -1, dtype=torch.int32, device="cuda")
+    bad = [dict(stats=torch.zeros(8, dtype=torch.int32, device="cuda")),
+           dict(stats=torch.zeros(4, dtype=torch.int64, device="cuda")),
+           dict(tile_cost=torch.zeros(nt - 1, dtype=torch.int64, device="cuda")),
+           dict(tile_time=torch.zeros(nt, dtype=torch.int64, device="cuda")),
+           dict(mode="ordered", order=torch.arange(nt, dtype=torch.int64, device="cuda")),
+           dict(mode="learned", mlp=torch.zeros(100, dtype=torch.float32, device="cuda"))]
+    for kw in bad:
+        with pytest.raises(ValueError):
+            plan.launch(out, **kw)
+    with pytest.raises(ValueError):
+        plan.launch(out[:-1])
+    torch.cuda.synchronize()
+    assert int(out.max().item()) == -1          # nothing ran
+    v = views[0]
+    with pytest.raises(ValueError):
+        native.render_sched(v.window, v.m, v.n, v.max_iter, v.R,
+                            claims=torch.zeros(3, dtype=torch.int32, device="cuda"))
+    with pytest.raises(ValueError):
+        native.order_desc(torch.zeros(10, dtype=torch.float64, device="cuda"))
+    plan.close()

@@ -116,3 +116,18 @@ def test_dd_invalid_arguments(kw):
 def test_dd_empty_image_is_a_no_op():
     assert _call_dd(m=0, out=None) == native.OK
     assert native.lib().mandel_render_dd(None, 4, 4, 10, 2.0, 0x1000, None, None) == native.EINVAL
+
+
+def test_binding_checks_buffers_before_the_library():
+    # every optional device buffer is checked for element type, contiguity, size and
+    # GPU residence before its pointer reaches the C ABI (None passes as NULL)
+    import torch
+    assert native._dev(None, torch.int64, 8, "stats") is None
+    with pytest.raises(ValueError, match="stats must be"):
+        native._dev(torch.zeros(8, dtype=torch.int32), native._i64(), 8, "stats")
+    with pytest.raises(ValueError, match="contiguous"):
+        native._dev(torch.zeros(8, 2, dtype=torch.int64).t(), native._i64(), 8, "stats")
+    with pytest.raises(ValueError, match="needs at least 8"):
+        native._dev(torch.zeros(7, dtype=torch.int64), native._i64(), 8, "stats")
+    with pytest.raises(ValueError, match="GPU tensor"):
+        native._dev(torch.zeros(8, dtype=torch.int64), native._i64(), 8, "stats")
