@@ -134,22 +134,31 @@ def quick_model():
 
 
 def test_bench_configuration_8192(quick_model):
-    # The launch the benchmark times, at full size: one-view plan of the 8192 x 8192 view,
-    # learned order, hipGraph replay.  Sampled pixels against the oracle; symmetry of
-    # the whole image; equality with the plain FCFS entry point.
+    # The launches the benchmark times, at full size and in its configuration: two
+    # one-view plans of the 8192 x 8192 view, learned order, hipGraph replays,
+    # consecutive steps alternating over two streams so that they overlap.  Both
+    # buffers: symmetry of the whole image, equality with the plain FCFS entry point,
+    # sampled pixels against the oracle.
     v = workloads.c2()
-    plan = native.Plan([v])
-    out = torch.full((plan.out_size(),), -1, dtype=torch.int32, device="cuda")
-    for rep in range(2):
-        plan.launch(out, mode="learned", mlp=quick_model, use_graph=True)
+    plans = [native.Plan([v]), native.Plan([v])]
+    outs = [torch.full((plans[0].out_size(),), -1, dtype=torch.int32, device="cuda")
+            for _ in range(2)]
+    streams = [torch.cuda.current_stream(), torch.cuda.Stream()]
     torch.cuda.synchronize()
-    img = out.view(v.m, v.n)
-    assert torch.equal(img, img.flip(0))
+    for k in range(6):
+        i = k % 2
+        plans[i].launch(outs[i], mode="learned", mlp=quick_model, use_graph=True,
+                        stream=streams[i])
+    torch.cuda.synchronize()
     plain = native.render(v.window, v.m, v.n, v.max_iter, v.R)
     torch.cuda.synchronize()
-    assert torch.equal(plain, img)
-    _sample_check(plan, out, np.random.default_rng(8192), per_view=3000)
-    plan.close()
+    for i in range(2):
+        img = outs[i].view(v.m, v.n)
+        assert torch.equal(img, img.flip(0))
+        assert torch.equal(plain, img)
+    _sample_check(plans[0], outs[0], np.random.default_rng(8192), per_view=3000)
+    for p in plans:
+        p.close()
 
 
 def test_bench_configuration_batch(quick_model):
