@@ -23,8 +23,10 @@
  *     one small workspace (a 256-byte queue head and a 32 KiB order histogram)
  *     per (device, stream) it has seen, until the process ends.  Calls that
  *     overlap in time on different streams never share a workspace.
- *   - Return value: MANDEL_OK (0) or a negative code.  On error nothing is
- *     enqueued, and mandel_last_error() returns a description (thread-local).
+ *   - Return value: MANDEL_OK (0) or a negative code, and mandel_last_error()
+ *     returns a description (thread-local).  An invalid argument (-1) or a
+ *     failed allocation (-2) enqueues nothing; a HIP runtime error (-3) in the
+ *     middle of a sequence of kernels can leave the kernels before it enqueued.
  *     No C++ exception crosses this interface.
  */
 #ifndef MANDEL_H
@@ -102,7 +104,7 @@ typedef struct mandel_window_dd {
  * queue of 64 x 8 tiles.  stats: NULL or device uint64[4] accumulated over
  * calls ([0] wavefront steps, [1] sum of counts, [2] wavefronts, [3] tiles).
  * Same argument limits as mandel_render, and every pixel centre must lie within
- * |re|, |im| <= 1e150.  Returns 0, or -1 EINVAL / -3 EHIP with nothing enqueued.
+ * |re|, |im| <= 1e150.  Returns 0, -1 EINVAL (nothing enqueued) or -3 EHIP.
  */
 int mandel_render_dd(const mandel_window_dd *w, int32_t m, int32_t n, int32_t max_iter,
                      double R, int32_t *out, uint64_t *stats, void *stream);
@@ -336,7 +338,7 @@ typedef struct mandel_launch {
  * and the first launch with steal = 1 its row counters and held-tile table
  * (4 bytes per tile and per wavefront), with hipMalloc (synchronous; -2 ENOMEM
  * on failure); they live until mandel_plan_destroy.  Returns 0, or -1 EINVAL /
- * -2 ENOMEM / -3 EHIP with nothing enqueued.
+ * -2 ENOMEM (nothing enqueued) / -3 EHIP.
  */
 int mandel_plan_launch(mandel_plan *plan, int32_t *out_base, const mandel_launch *args,
                        void *stream);

@@ -429,10 +429,12 @@ int mandel_plan_launch(mandel_plan *p, int32_t *out, const mandel_launch *args, 
         return hip_fail(e, "hipStreamBeginCapture");
     int rc = enqueue(p, out, la, p->capture);
     e = hipStreamEndCapture(p->capture, &g.graph);
-    if (rc)
-        return rc;
-    if (e != hipSuccess)
-        return hip_fail(e, "hipStreamEndCapture");
+    if (rc || e != hipSuccess) {
+        // nothing ran: drop whatever the capture recorded
+        if (e == hipSuccess && g.graph)
+            (void)hipGraphDestroy(g.graph);
+        return rc ? rc : hip_fail(e, "hipStreamEndCapture");
+    }
     e = hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0);
     if (e != hipSuccess) {
         (void)hipGraphDestroy(g.graph);
