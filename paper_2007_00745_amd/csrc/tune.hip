@@ -133,6 +133,8 @@ extern "C" int mandel_plan_autotune(const mandel_view *views, int32_t nviews, in
     if (e == hipSuccess)
         e = hipEventCreate(&e1);
     if (e != hipSuccess) {
+        if (e0)
+            (void)hipEventDestroy(e0);
         (void)hipFree(scratch);
         return hip_fail(e, "hipEventCreate");
     }
