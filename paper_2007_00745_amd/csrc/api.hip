@@ -104,7 +104,8 @@ int64_t tile_count(int32_t m, int32_t n, int32_t tw, int32_t th)
 {
     if (m <= 0 || n <= 0 || tw <= 0 || th <= 0)
         return 0;
-    return (int64_t)((m + th - 1) / th) * (int64_t)((n + tw - 1) / tw);
+    // in 64 bits: m + th - 1 overflows int32 for m near 2^31
+    return (((int64_t)m + th - 1) / th) * (((int64_t)n + tw - 1) / tw);
 }
 
 // Fills d (all but out_off and tile_off) from one view's arguments.
@@ -153,8 +154,8 @@ int make_view(const mandel_window *w, int32_t m, int32_t n, int32_t max_iter, do
     d->m = m;
     d->n = n;
     d->max_iter = max_iter;
-    d->tiles_x = (n + tile_w - 1) / tile_w;
-    d->tiles_y = (m + tile_h - 1) / tile_h;
+    d->tiles_x = (int32_t)(((int64_t)n + tile_w - 1) / tile_w);
+    d->tiles_y = (int32_t)(((int64_t)m + tile_h - 1) / tile_h);
     return MANDEL_OK;
 }
 

@@ -131,3 +131,12 @@ def test_binding_checks_buffers_before_the_library():
         native._dev(torch.zeros(7, dtype=torch.int64), native._i64(), 8, "stats")
     with pytest.raises(ValueError, match="GPU tensor"):
         native._dev(torch.zeros(8, dtype=torch.int64), native._i64(), 8, "stats")
+
+
+def test_tile_count_at_extreme_sizes():
+    # ceil divisions in 64 bits: m or n near 2^31 must not overflow
+    big = 2 ** 31 - 1
+    assert native.tile_count(big, 1, 64, 8) == (big + 7) // 8
+    assert native.tile_count(1, big, 64, 8) == (big + 63) // 64
+    assert native.tile_count(big, 1, 1, 2 ** 20) == (big + 2 ** 20 - 1) // 2 ** 20
+    assert native.tile_count(46341, 46341, 64, 8) == 5793 * 725
