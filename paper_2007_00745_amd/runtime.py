@@ -12,6 +12,7 @@ a stream watchdog.
 """
 from __future__ import annotations
 
+import fcntl
 import hashlib
 import json
 import os
@@ -25,25 +26,39 @@ def batch_signature(views) -> str:
     return hashlib.sha256(json.dumps(items).encode()).hexdigest()[:24]
 
 
+def _read_table(path: str) -> dict:
+    if not os.path.exists(path):
+        return {}
+    with open(path) as f:
+        return json.load(f)
+
+
 def autotune_cached(views, path: str, max_sample: int = 8, device_name: str | None = None,
                     stream=None) -> tuple[dict, bool]:
-    """(tuning, came_from_file).  The file is rewritten atomically on a miss."""
+    """(tuning, came_from_file).  A miss autotunes and adds the entry while holding an
+    advisory lock on `path`.lock, then rewrites the file atomically, so processes
+    that share the file neither lose each other's entries nor tune one batch twice."""
     if device_name is None:
         import torch
         device_name = torch.cuda.get_device_name()
     key = f"{device_name}|{batch_signature(views)}"
-    table = {}
-    if os.path.exists(path):
-        with open(path) as f:
-            table = json.load(f)
+    table = _read_table(path)
     if key in table:
         return dict(table[key]), True
-    tuning, _ = native.autotune(views, max_sample=max_sample, stream=stream)
-    table[key] = tuning
-    tmp = f"{path}.tmp{os.getpid()}"
-    with open(tmp, "w") as f:
-        json.dump(table, f, indent=1, sort_keys=True)
-    os.replace(tmp, path)
+    with open(f"{path}.lock", "a") as lock:
+        fcntl.flock(lock, fcntl.LOCK_EX)
+        try:
+            table = _read_table(path)          # another process may have added it
+            if key in table:
+                return dict(table[key]), True
+            tuning, _ = native.autotune(views, max_sample=max_sample, stream=stream)
+            table[key] = tuning
+            tmp = f"{path}.tmp{os.getpid()}"
+            with open(tmp, "w") as f:
+                json.dump(table, f, indent=1, sort_keys=True)
+            os.replace(tmp, path)
+        finally:
+            fcntl.flock(lock, fcntl.LOCK_UN)
     return tuning, False
 
 

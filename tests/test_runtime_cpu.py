@@ -47,3 +47,28 @@ def test_autotune_cache_file(tmp_path, monkeypatch):
     assert (hit1, hit2, hit3) == (False, True, False) and calls == [1, 1]
     assert t1 == t2 == t3 == {"tile_w": 32, "tile_h": 4}
     assert len(json.load(open(path))) == 2
+
+
+def _tune_in_child(path, m, q):
+    # a separate process adds its own batch to the shared cache file
+    from paper_2007_00745_amd import native as nat, runtime as rt, workloads as wl
+    nat.autotune = lambda v, max_sample=8, stream=None: ({"tile_w": 8 + m % 7, "tile_h": 4}, 1)
+    q.put(rt.autotune_cached([wl.View((0.0, 0.0, 1e-3, 1e-3), m, 16, 100)], path,
+                             device_name="dev0")[1])
+
+
+def test_autotune_cache_file_shared_by_processes(tmp_path):
+    # eight processes add eight different batches at once: no entry is lost
+    import multiprocessing as mp
+    path = str(tmp_path / "tune.json")
+    ctx = mp.get_context("spawn")
+    q = ctx.Queue()
+    procs = [ctx.Process(target=_tune_in_child, args=(path, 10 + k, q)) for k in range(8)]
+    for p in procs:
+        p.start()
+    for p in procs:
+        p.join(60)
+        assert p.exitcode == 0
+    hits = [q.get(timeout=5) for _ in procs]
+    assert hits == [False] * 8
+    assert len(json.load(open(path))) == 8
