@@ -724,7 +724,7 @@ render_kernel(RenderArgs a)
                             if (mine)
                                 skipped += deadline - W;
                             finalize(mine, false);
-                            if (em == 0 && (uint32_t)__popcll(~ballot(active)) >= R)
+                            if (em == 0 && (uint32_t)__popcll(~ballot(active)) >= Rs)
                                 break; // enough idle lanes: refill them
                         }
                     }
