@@ -278,19 +278,26 @@ def paper_context(torch, native, workloads) -> dict:
             "time_ratio": paper_s / (ms / 1e3)}
 
 
-def timed_ms(torch, fn, reps: int, name: str) -> float:
+def timed_stats(torch, fn, reps: int, name: str) -> dict:
+    """One untimed warm-up call, then `reps` calls each between two events:
+    {"ms": minimum, "median_ms": median, "reps": reps}."""
     fn()
     torch.cuda.synchronize()
-    best = float("inf")
+    ts = []
     for r in range(reps):
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         a.record()
         fn()
         b.record()
         torch.cuda.synchronize()
-        best = min(best, a.elapsed_time(b))
-        log(f"  {name} rep {r}: {a.elapsed_time(b):.2f} ms")
-    return best
+        ts.append(a.elapsed_time(b))
+        log(f"  {name} rep {r}: {ts[-1]:.2f} ms")
+    ts.sort()
+    return {"ms": ts[0], "median_ms": ts[len(ts) // 2], "reps": reps}
+
+
+def timed_ms(torch, fn, reps: int, name: str) -> float:
+    return timed_stats(torch, fn, reps, name)["ms"]
 
 
 def tail_fraction(st, clock_khz):
@@ -348,6 +355,8 @@ def makespans(torch, native, workloads, costmodel, reps: int, clock_khz: float,
             native.render_sched(v.window, v.m, v.n, v.max_iter, v.R,
                                 out=out[o:o + v.pixels].view(v.m, v.n), **kw)
 
+    # Each configuration is swept once; the best worker count is then timed `reps` times
+    # (min and median reported, speed-ups on the min).
     ms = {}
     for pol in ("static", "alternating"):
         best = None
@@ -355,10 +364,11 @@ def makespans(torch, native, workloads, costmodel, reps: int, clock_khz: float,
                             ("W=m/4", lambda v: max(1, v.m // 4))):
             t = timed_ms(torch, lambda: per_view(pol, wsel), 1, f"{pol} {label}")
             if best is None or t < best[0]:
-                best = (t, label)
-        ms[f"{pol}_rows_per_view"] = {"ms": best[0], "workers": best[1]}
+                best = (t, label, wsel)
+        rec = timed_stats(torch, lambda: per_view(pol, best[2]), reps, f"{pol} {best[1]}")
+        ms[f"{pol}_rows_per_view"] = dict(rec, workers=best[1])
     assert torch.equal(out, ref), "row partitions changed the counts"
-    ms["fcfs_per_view"] = {"ms": timed_ms(torch, lambda: per_view("fcfs", None), 1, "fcfs/view")}
+    ms["fcfs_per_view"] = timed_stats(torch, lambda: per_view("fcfs", None), reps, "fcfs/view")
 
     # The stricter static baseline: one launch in which the rows of all 64 views,
     # concatenated, are split over W workgroups by the paper's partitions.  W = 7 per CU
@@ -374,13 +384,14 @@ def makespans(torch, native, workloads, costmodel, reps: int, clock_khz: float,
                                 f"concatenated {pol} W={W}")
             assert torch.equal(out, ref), f"concatenated {pol} changed the counts"
         W = min(per_w, key=per_w.get)
+        rec = timed_stats(torch, lambda: plan.launch(out, mode=pol, workers=W, use_graph=True),
+                          reps, f"concatenated {pol} W={W}")
         stats.zero_()
         plan.launch(out, mode=pol, workers=W, stats=stats)
         torch.cuda.synchronize()
         st = [int(v) for v in stats.cpu().tolist()]
-        ms[f"{pol}_rows_concatenated"] = {"ms": per_w[W], "workers": W,
-                                          "ms_by_workers": per_w,
-                                          "tail": tail_fraction(st, clock_khz)}
+        ms[f"{pol}_rows_concatenated"] = dict(rec, workers=W, ms_by_workers=per_w,
+                                              tail=tail_fraction(st, clock_khz))
 
     res["cost_model_eval"] = costmodel.evaluate(params, plan.features(),
                                                 native.cost_targets(cost))
@@ -390,14 +401,14 @@ def makespans(torch, native, workloads, costmodel, reps: int, clock_khz: float,
     for mode, kw in (("fcfs", {}), ("probe", {}), ("learned", {"mlp": params}),
                      ("ordered", {"order": true_perm})):
         out.fill_(-1)
-        t = timed_ms(torch, lambda: plan.launch(out, mode=mode, use_graph=True, **kw), reps,
-                     f"batched {mode}")
+        rec = timed_stats(torch, lambda: plan.launch(out, mode=mode, use_graph=True, **kw),
+                          reps, f"batched {mode}")
         assert torch.equal(out, ref), f"batched {mode} changed the counts"
         stats.zero_()
         plan.launch(out, mode=mode, stats=stats, **kw)
         torch.cuda.synchronize()
         st = [int(v) for v in stats.cpu().tolist()]
-        ms[f"batched_{names[mode]}"] = {"ms": t, "tail": tail_fraction(st, clock_khz)}
+        ms[f"batched_{names[mode]}"] = dict(rec, tail=tail_fraction(st, clock_khz))
     res["makespan_ms"] = ms
     static = min(ms["static_rows_per_view"]["ms"], ms["alternating_rows_per_view"]["ms"])
     res["speedup_batched_learned_vs_static_rows"] = static / ms["batched_learned_lpt"]["ms"]
@@ -406,6 +417,15 @@ def makespans(torch, native, workloads, costmodel, reps: int, clock_khz: float,
     res["speedup_batched_learned_vs_concatenated_rows"] = concat / ms["batched_learned_lpt"]["ms"]
     res["speedup_batched_fcfs_vs_concatenated_rows"] = concat / ms["batched_fcfs"]["ms"]
     res["batched_fcfs_pixel_iterations_per_s"] = sum_counts / (ms["batched_fcfs"]["ms"] / 1e3)
+    static_med = min(ms["static_rows_per_view"]["median_ms"],
+                     ms["alternating_rows_per_view"]["median_ms"])
+    concat_med = min(ms["static_rows_concatenated"]["median_ms"],
+                     ms["alternating_rows_concatenated"]["median_ms"])
+    res["speedup_medians"] = {
+        "batched_learned_vs_static_rows": static_med / ms["batched_learned_lpt"]["median_ms"],
+        "batched_fcfs_vs_static_rows": static_med / ms["batched_fcfs"]["median_ms"],
+        "batched_learned_vs_concatenated_rows": concat_med / ms["batched_learned_lpt"]["median_ms"],
+        "batched_fcfs_vs_concatenated_rows": concat_med / ms["batched_fcfs"]["median_ms"]}
     plan.close()
     return res
 
@@ -541,7 +561,7 @@ def main():
     ap.add_argument("--max-iter", type=int, default=10000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-makespan", action="store_true")
-    ap.add_argument("--makespan-reps", type=int, default=3)
+    ap.add_argument("--makespan-reps", type=int, default=5)
     ap.add_argument("--no-stress", action="store_true",
                     help="skip the stress batch (16384^2 deep zoom + 4096 views of 512^2)")
     ap.add_argument("--stress-contiguous-rows", action="store_true",
