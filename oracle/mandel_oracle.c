@@ -16,7 +16,7 @@
  *   which |z|^2 first exceeds the escape radius squared, or iterationMax if
  *   that never happens, is recorded as I[i][j].
  *
- * Readings where the paper is silent (each one is listed in the design doc):
+ * Readings where the paper is silent:
  *   - the test is |z|^2 > R*R, strict (the paper says the magnitude must
  *     exceed the escape radius);
  *   - count = min(max_iter, first k >= 1 with |z_k|^2 > R^2), so 1 <= count
