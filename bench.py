@@ -507,6 +507,47 @@ def comparisons(torch, native, view, plan, out, cost, sum_counts, stream) -> dic
     return comp
 
 
+def view_partitions(torch, native, view, ref, sum_counts, cus: int, clock_khz: float,
+                    headline_ms: float) -> dict:
+    """The paper's setting on one image, the 8192 x 8192 view: its contiguous rows
+    (Sec. III-A, Eq. (stp)-(rem)) and alternating rows (Sec. III-C) over W workgroup
+    workers, against the device FCFS tile queue (Sec. III-B's analogue; 64 x 8 tiles,
+    claim grain swept) and the non-persistent grid launch.  Every image must equal the
+    headline's."""
+    res = {}
+    out = torch.empty((view.m, view.n), dtype=torch.int32, device="cuda")
+    stats = torch.zeros(8, dtype=torch.int64, device="cuda")
+
+    def run(name, **sched):
+        rec = timed_stats(torch, lambda: native.render_sched(view.window, view.m, view.n,
+                                                             view.max_iter, view.R, out=out,
+                                                             **sched), 3, name)
+        assert torch.equal(out.view(-1), ref), f"{name} changed the counts"
+        stats.zero_()
+        native.render_sched(view.window, view.m, view.n, view.max_iter, view.R, out=out,
+                            stats=stats, **sched)
+        torch.cuda.synchronize()
+        st = [int(v) for v in stats.cpu().tolist()]
+        rec["pixel_iterations_per_s"] = sum_counts / (rec["ms"] / 1e3)
+        rec["tail"] = tail_fraction(st, clock_khz)
+        return rec
+
+    for pol in ("static", "alternating"):
+        per = {}
+        for W in (256, 512, 1024, 2048, cus * 7):
+            per[W] = run(f"{pol} rows W={W}", policy=pol, workers=W)
+        best = min(per, key=lambda w: per[w]["ms"])
+        res[f"{pol}_rows"] = {"by_workers": per, "best_workers": best, "best_ms": per[best]["ms"]}
+    per = {g: run(f"fcfs grain {g}", grain=g) for g in (1, 2, 4, 8)}
+    best = min(per, key=lambda g: per[g]["ms"])
+    res["fcfs_tiles"] = {"by_grain": per, "best_grain": best, "best_ms": per[best]["ms"]}
+    res["grid_tiles"] = run("grid", policy="grid")
+    best_rows = min(res["static_rows"]["best_ms"], res["alternating_rows"]["best_ms"])
+    res["speedup_fcfs_vs_best_row_partition"] = best_rows / res["fcfs_tiles"]["best_ms"]
+    res["speedup_headline_step_vs_best_row_partition"] = best_rows / headline_ms
+    return res
+
+
 FP32_PEAK_TFLOPS = 157.3  # MI355X FP32 vector (FMA = 2 flops)
 HBM_PEAK_GBS = 8000.0
 
@@ -722,6 +763,9 @@ def main():
         log(f"bench: fp64 ceilings fma {ceiling['fma_chain']['tflops']:.1f}, update loop "
             f"{best:.1f} TFLOP/s")
         comp = comparisons(torch, native, view, plan, out, cost, sum_counts, stream)
+        comp["paper_partitions_one_view"] = view_partitions(
+            torch, native, view, out.clone(), sum_counts, int(dinfo["compute_units"]),
+            clock_khz, ms_mean)
         comp["render_kernel_ms"] = render_ms
         per = periodicity(torch, native, view, plan, out, sum_counts, serial["ms_mean"],
                           clock_khz, stream)
