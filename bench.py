@@ -15,7 +15,9 @@ steps, events on both streams); the one-stream step time is reported beside it.
 FP64 FLOP/s counts 7 operations per iteration (x*x, y*y, x*y, 2*, -, +cx, +cy).
 
 Also reported (not the value): the plain mandel_render (FCFS queue in tile
-order) and the order by true tile costs on the same view; the time to the same
+order) and the order by true tile costs on the same view; the paper's contiguous
+and alternating row partitions of the same view over 256..2048 workers, the FCFS
+queue's claim grain and the grid launch; the time to the same
 image with exact periodicity detection (updates skipped reported apart, never
 counted as executed); the paper's image shape (8000 x 8000, max_iter 2000,
 R 400, window assumed) next to the paper's 32-task computation time; makespans
