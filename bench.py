@@ -119,8 +119,28 @@ def cpu_baseline(view, rows_step: int, threads: int) -> dict:
     img = oracle.render(c1.window, c1.m, c1.n, c1.max_iter, c1.R)
     d1 = time.perf_counter() - t1
     s1 = int(img.sum(dtype=np.int64))
+    import platform
+    import subprocess
+    try:
+        gcc = subprocess.run(["gcc", "--version"], capture_output=True, text=True,
+                             timeout=10).stdout.splitlines()[0]
+    except (OSError, subprocess.SubprocessError, IndexError):
+        gcc = None
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    host = {"cpu_model": model or platform.processor() or None,
+            "nproc": os.cpu_count(),
+            "usable_cpus": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity")
+            else None,
+            "compiler": gcc, "cflags": " ".join(oracle.CFLAGS)}
     return {"value": total / dt, "unit": "pixel-iterations/s", "cores": threads,
-            "kind": "oracle",
+            "kind": "oracle", "host": host,
             "sample": f"rows i = 0 mod {rows_step} of the {view.m}x{view.n} view "
                       f"({len(rows)} rows, {idx.size} px, {total} iterations, {dt:.2f} s wall)",
             "single_core": {"value": s1 / d1, "seconds": d1, "iterations": s1,
