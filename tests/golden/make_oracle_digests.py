@@ -1,0 +1,61 @@
+"""Writes tests/golden/oracle_digests.json: for every view of the 640 x 480 view (c1),
+the 8192 x 8192 view at max_iter 10000 (c2) and the uneven 64-view batch (c3, seed
+745), the SHA-256 of the oracle's image (int32, little-endian, row-major) and its sum
+of counts.  Only the CPU oracle computes the images (one single-threaded worker per
+row band); the views come from the seeded input generator.  The GPU tests compare the
+digests of whole GPU images with these, so every pixel of these workloads is checked
+bit for bit without re-running the oracle on the test machine.
+
+    python tests/golden/make_oracle_digests.py [--threads T] [--only c1,c2,c3]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+OUT = os.path.join(ROOT, "tests", "golden", "oracle_digests.json")
+
+
+def digest(img) -> str:
+    import numpy as np
+    return hashlib.sha256(np.ascontiguousarray(img, dtype="<i4").tobytes()).hexdigest()
+
+
+def main() -> int:
+    import oracle
+    from paper_2007_00745_amd import workloads
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--threads", type=int, default=os.cpu_count() or 1)
+    ap.add_argument("--only", default="c1,c2,c3")
+    args = ap.parse_args()
+    table = json.load(open(OUT)) if os.path.exists(OUT) else {}
+    sets = {"c1": lambda: [workloads.c1()], "c2": lambda: [workloads.c2()],
+            "c3": workloads.c3}
+    for name in args.only.split(","):
+        rows = []
+        t0 = time.time()
+        for k, v in enumerate(sets[name]()):
+            img, _ = oracle.render_parallel(v.window, v.m, v.n, v.max_iter, v.R,
+                                            threads=args.threads)
+            rows.append({"view": k, "m": v.m, "n": v.n, "max_iter": v.max_iter, "R": v.R,
+                         "window": [float(x).hex() for x in v.window],
+                         "sha256": digest(img), "sum": int(img.sum(dtype="int64"))})
+            print(f"{name} view {k}: {v.m}x{v.n} max_iter {v.max_iter} "
+                  f"sum {rows[-1]['sum']} ({time.time() - t0:.0f} s)", flush=True)
+        table[name] = rows
+        tmp = OUT + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump(table, f, indent=1, sort_keys=True)
+        os.replace(tmp, OUT)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

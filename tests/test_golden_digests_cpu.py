@@ -1,0 +1,46 @@
+"""The stored whole-image digests of the oracle (tests/golden/oracle_digests.json,
+written by tests/golden/make_oracle_digests.py, which calls only the oracle) are
+pinned here: the 640 x 480 view's digest is recomputed with the oracle, and every
+stored view's size, max_iter, R and window must still be what the seeded input
+generator produces, so a changed generator cannot silently compare against stale
+digests."""
+import hashlib
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2007_00745_amd import workloads
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                      "oracle_digests.json")
+
+
+def _table():
+    return json.load(open(GOLDEN))
+
+
+def test_c1_digest_recomputed_by_the_oracle():
+    g = _table()["c1"][0]
+    v = workloads.c1()
+    img = oracle.render(v.window, v.m, v.n, v.max_iter, v.R)
+    assert int(img.sum(dtype=np.int64)) == g["sum"]
+    assert hashlib.sha256(np.ascontiguousarray(img, dtype="<i4").tobytes()).hexdigest() == g["sha256"]
+
+
+@pytest.mark.parametrize("name,views", [("c1", lambda: [workloads.c1()]),
+                                        ("c2", lambda: [workloads.c2()]),
+                                        ("c3", workloads.c3)])
+def test_stored_views_match_the_generator(name, views):
+    table = _table()
+    if name not in table:
+        pytest.skip(f"{name} digests not generated")
+    stored = table[name]
+    vs = views()
+    assert len(stored) == len(vs)
+    for g, v in zip(stored, vs):
+        assert (g["m"], g["n"], g["max_iter"], g["R"]) == (v.m, v.n, v.max_iter, v.R)
+        assert [float.fromhex(x) for x in g["window"]] == [float(x) for x in v.window]
+        assert 0 < g["sum"] <= v.m * v.n * v.max_iter

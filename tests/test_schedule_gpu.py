@@ -2,6 +2,9 @@
 order against FCFS (what the trained cost model gains, measured), and the
 stress batch (a 16384 x 16384 deep zoom of width 1e-12 plus 4096 views of
 512 x 512).  Every schedule must give the same counts as the CPU oracle."""
+import hashlib
+import json
+import os
 import sys
 
 import numpy as np
@@ -30,6 +33,22 @@ def _timed(fn, reps=3):
         torch.cuda.synchronize()
         best = min(best, a.elapsed_time(b))
     return best
+
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                      "oracle_digests.json")
+
+
+def _golden(name):
+    # whole-image digests of the oracle (tests/golden/make_oracle_digests.py), or None
+    # while they have not been generated for this workload
+    if not os.path.exists(GOLDEN):
+        return None
+    return json.load(open(GOLDEN)).get(name)
+
+
+def _digest(img_cpu):
+    return hashlib.sha256(np.ascontiguousarray(img_cpu.numpy(), dtype="<i4").tobytes()).hexdigest()
 
 
 def _sample_check(plan, out, rng, per_view=256, max_views=None):
@@ -157,6 +176,13 @@ def test_bench_configuration_8192(quick_model):
         assert torch.equal(img, img.flip(0))
         assert torch.equal(plain, img)
     _sample_check(plans[0], outs[0], np.random.default_rng(8192), per_view=3000)
+    gold = _golden("c2")
+    if gold is not None:
+        # every pixel of both buffers against the oracle's whole image
+        for i in range(2):
+            img = outs[i].cpu()
+            assert int(img.sum(dtype=torch.int64)) == gold[0]["sum"]
+            assert _digest(img) == gold[0]["sha256"]
     for p in plans:
         p.close()
 
@@ -172,6 +198,14 @@ def test_bench_configuration_batch(quick_model):
     torch.cuda.synchronize()
     assert int(out.min().item()) >= 1
     _sample_check(plan, out, np.random.default_rng(745), per_view=48)
+    gold = _golden("c3")
+    if gold is not None:
+        # every pixel of every view against the oracle's whole images
+        imgs = plan.view_images(out.cpu())
+        assert len(gold) == len(imgs)
+        for k, (img, g) in enumerate(zip(imgs, gold)):
+            assert int(img.sum(dtype=torch.int64)) == g["sum"], f"view {k}"
+            assert _digest(img) == g["sha256"], f"view {k}"
     plan.close()
 
 
