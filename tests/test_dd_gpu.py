@@ -138,3 +138,22 @@ def test_deep_view_2048_sampled():
     want = dd_oracle.render_pixels(win, m, n, 50000, 2.0, idx, threads=16)
     assert np.array_equal(got, want)
     assert int(img.min()) >= 1 and int(img.max()) <= 50000
+
+
+def test_deep_zoom_bench_view_whole_image():
+    # The deep-zoom view the benchmark times (4096 x 4096 at pitch 1e-17, max_iter 20000):
+    # every pixel against the double-double oracle's whole image, through its stored
+    # digest (tests/golden/make_oracle_digests.py).
+    import hashlib
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                        "oracle_digests.json")
+    table = json.load(open(path)) if os.path.exists(path) else {}
+    if "dd_deep" not in table:
+        pytest.skip("double-double digest not generated")
+    g = table["dd_deep"][0]
+    win = tuple(float.fromhex(x) for x in g["window"])
+    got = _gpu(win, g["m"], g["n"], g["max_iter"], g["R"])
+    assert int(got.sum(dtype=np.int64)) == g["sum"]
+    assert hashlib.sha256(np.ascontiguousarray(got, dtype="<i4").tobytes()).hexdigest() == g["sha256"]

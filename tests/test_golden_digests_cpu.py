@@ -44,3 +44,18 @@ def test_stored_views_match_the_generator(name, views):
         assert (g["m"], g["n"], g["max_iter"], g["R"]) == (v.m, v.n, v.max_iter, v.R)
         assert [float.fromhex(x) for x in g["window"]] == [float(x) for x in v.window]
         assert 0 < g["sum"] <= v.m * v.n * v.max_iter
+
+
+def test_stored_deep_zoom_view_matches_its_definition():
+    import importlib.util
+    table = _table()
+    if "dd_deep" not in table:
+        pytest.skip("double-double digest not generated")
+    spec = importlib.util.spec_from_file_location(
+        "make_oracle_digests", os.path.join(os.path.dirname(GOLDEN), "make_oracle_digests.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    d, g = mod.DD_DEEP, table["dd_deep"][0]
+    assert (g["m"], g["n"], g["max_iter"], g["R"]) == (d["m"], d["n"], d["max_iter"], d["R"])
+    assert [float.fromhex(x) for x in g["window"]] == list(d["window"])
+    assert 0 < g["sum"] <= d["m"] * d["n"] * d["max_iter"]
