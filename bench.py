@@ -618,7 +618,7 @@ def secondary_kernels(torch, native, plan, params, sum_probe_iters, reps: int) -
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--side", type=int, default=8192)
     ap.add_argument("--max-iter", type=int, default=10000)

@@ -3,12 +3,13 @@ the 8192 x 8192 view at max_iter 10000 (c2) and the uneven 64-view batch (c3, se
 745), the SHA-256 of the oracle's image (int32, little-endian, row-major) and its sum
 of counts; and the same for the double-double oracle's image of the deep-zoom view
 (dd_deep: 4096 x 4096 at pitch 1e-17 around -0.7436438870371587 + 0.1318259042053119 i,
-max_iter 20000, R 2).  Only the CPU oracle computes the images (one single-threaded worker per
+max_iter 20000, R 2); and one digest over the concatenated images of the 4096 small
+views of the stress batch (c5 without its deep view, which is beyond a CPU run).  Only the CPU oracle computes the images (one single-threaded worker per
 row band); the views come from the seeded input generator.  The GPU tests compare the
 digests of whole GPU images with these, so every pixel of these workloads is checked
 bit for bit without re-running the oracle on the test machine.
 
-    python tests/golden/make_oracle_digests.py [--threads T] [--only c1,c2,c3,dd_deep]
+    python tests/golden/make_oracle_digests.py [--threads T] [--only c1,c2,c3,dd_deep,c5_small]
 """
 from __future__ import annotations
 
@@ -56,6 +57,25 @@ def dd_deep(threads: int) -> dict:
             "sha256": digest(img), "sum": int(img.sum(dtype="int64"))}
 
 
+def c5_small(threads: int) -> dict:
+    """One digest over the images of the stress batch's small views, concatenated in
+    submission order (views 1 .. 4096 of c5), and their total sum of counts."""
+    import oracle
+    from paper_2007_00745_amd import workloads
+    views = workloads.c5()[1:]
+    h = hashlib.sha256()
+    total = 0
+    t0 = time.time()
+    for k, v in enumerate(views):
+        img, _ = oracle.render_parallel(v.window, v.m, v.n, v.max_iter, v.R, threads=threads)
+        h.update(img.astype("<i4", copy=False).tobytes())
+        total += int(img.sum(dtype="int64"))
+        if k % 256 == 0:
+            print(f"c5_small view {k + 1} ({time.time() - t0:.0f} s)", flush=True)
+    return {"views": len(views), "first_view": 1, "sha256": h.hexdigest(), "sum": total,
+            "m": views[0].m, "n": views[0].n}
+
+
 def main() -> int:
     import oracle
     from paper_2007_00745_amd import workloads
@@ -71,6 +91,8 @@ def main() -> int:
         t0 = time.time()
         if name == "dd_deep":
             rows.append(dd_deep(args.threads))
+        elif name == "c5_small":
+            rows.append(c5_small(args.threads))
         else:
             for k, v in enumerate(sets[name]()):
                 img, _ = oracle.render_parallel(v.window, v.m, v.n, v.max_iter, v.R,

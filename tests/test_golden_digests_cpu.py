@@ -59,3 +59,14 @@ def test_stored_deep_zoom_view_matches_its_definition():
     assert (g["m"], g["n"], g["max_iter"], g["R"]) == (d["m"], d["n"], d["max_iter"], d["R"])
     assert [float.fromhex(x) for x in g["window"]] == list(d["window"])
     assert 0 < g["sum"] <= d["m"] * d["n"] * d["max_iter"]
+
+
+def test_stored_stress_small_views_match_the_generator():
+    table = _table()
+    if "c5_small" not in table:
+        pytest.skip("stress-batch digest not generated")
+    g = table["c5_small"][0]
+    small = workloads.c5()[1:]
+    assert g["views"] == len(small) and g["first_view"] == 1
+    assert all((v.m, v.n) == (g["m"], g["n"]) for v in small)
+    assert 0 < g["sum"] <= sum(v.m * v.n * v.max_iter for v in small)

@@ -139,6 +139,20 @@ def test_stress_batch_c5():
                                 threads=16)
     assert np.array_equal(got, want)
     _sample_check(plan, out, rng, per_view=512, max_views=16)
+    gold = _golden("c5_small")
+    if gold is not None:
+        # every pixel of the 4096 small views (packed after the deep view, in order)
+        # against the oracle's images, through one digest over their concatenation
+        g = gold[0]
+        rest = out[deep.pixels:].cpu()
+        assert rest.numel() == g["views"] * g["m"] * g["n"]
+        assert int(rest.sum(dtype=torch.int64)) == g["sum"]
+        h = hashlib.sha256()
+        flat = rest.numpy()
+        step = 1 << 26
+        for a in range(0, flat.size, step):
+            h.update(np.ascontiguousarray(flat[a:a + step], dtype="<i4").tobytes())
+        assert h.hexdigest() == g["sha256"]
     plan.close()
 
 
