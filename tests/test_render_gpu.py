@@ -1,8 +1,8 @@
 """GPU parity: counts from libmandel.so (through the C ABI) against the CPU
 oracle, element by element and bit for bit (paper Sec. I, Eq. (1)-(2)), for
 every policy of the kernel family (Sec. III-A/B/C and the tile orders), both
-escape-test modes, ragged tile edges, degenerate sizes and radii, and the
-full-size 8192 x 8192 view on sampled pixels."""
+escape-test modes, ragged tile edges, degenerate sizes and radii, the
+full-size 8192 x 8192 view on sampled pixels, and output indices past 2^31."""
 import sys
 
 import numpy as np

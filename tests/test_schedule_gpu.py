@@ -1,7 +1,9 @@
 """GPU tests of the schedule layer: the autotuner, the learned longest-first
-order against FCFS (what the trained cost model gains, measured), and the
-stress batch (a 16384 x 16384 deep zoom of width 1e-12 plus 4096 views of
-512 x 512).  Every schedule must give the same counts as the CPU oracle."""
+order against FCFS (what the trained cost model gains, measured in time and as
+a list-scheduled makespan), the stress batch (a 16384 x 16384 deep zoom of width
+1e-12 plus 4096 views of 512 x 512), and the launches the benchmark times at full
+size.  Every schedule must give the same counts as the CPU oracle; whole images
+are compared with the oracle's stored digests (tests/golden)."""
 import hashlib
 import json
 import os
