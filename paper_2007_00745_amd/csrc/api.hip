@@ -215,8 +215,6 @@ int check_sched(const mandel_sched *s, mandel_sched *o)
         return fail(MANDEL_EINVAL, "first_slot applies to the queue policies only");
     if (d.tile_time && (d.policy == MANDEL_STATIC_ROWS || d.policy == MANDEL_ALTERNATING_ROWS))
         return fail(MANDEL_EINVAL, "tile_time applies to the tile policies only");
-    if (d.policy == MANDEL_ORDERED_TILES && !d.order)
-        return fail(MANDEL_EINVAL, "ORDERED_TILES needs an order array");
     *o = d;
     return MANDEL_OK;
 }
@@ -306,9 +304,11 @@ int mandel_render_sched(const mandel_window *w, int32_t m, int32_t n, int32_t ma
     if (rc)
         return rc;
     if (m == 0 || n == 0)
-        return MANDEL_OK;
+        return MANDEL_OK; // an empty image: nothing to order either
     if (!out)
         return fail(MANDEL_EINVAL, "out is NULL");
+    if (s.policy == MANDEL_ORDERED_TILES && !s.order)
+        return fail(MANDEL_EINVAL, "ORDERED_TILES needs an order array");
     hipStream_t st = (hipStream_t)stream;
     const bool rows = s.policy == MANDEL_STATIC_ROWS || s.policy == MANDEL_ALTERNATING_ROWS;
     const int64_t ntiles = rows ? (int64_t)m : tile_count(m, n, s.tile_w, s.tile_h);

@@ -359,10 +359,6 @@ int mandel_plan_launch(mandel_plan *p, int32_t *out, const mandel_launch *args, 
     }
     if (rows && la.steal)
         return fail(MANDEL_EINVAL, "row stealing applies to the queue modes only");
-    if (la.mode == MANDEL_PLAN_ORDERED && !la.order)
-        return fail(MANDEL_EINVAL, "ORDERED needs an order array");
-    if (la.mode == MANDEL_PLAN_LEARNED_LPT && !la.mlp)
-        return fail(MANDEL_EINVAL, "LEARNED_LPT needs model parameters");
     if (la.probe_cap == 0)
         la.probe_cap = 128;
     if (la.probe_cap < 1 || la.probe_cap > (1 << 20))
@@ -382,9 +378,13 @@ int mandel_plan_launch(mandel_plan *p, int32_t *out, const mandel_launch *args, 
     if (la.steal && p->ntiles > INT32_MAX)
         return fail(MANDEL_EINVAL, "row stealing supports at most 2^31 - 1 tiles");
     if (p->ntiles == 0)
-        return MANDEL_OK;
+        return MANDEL_OK; // no tiles: nothing to order, no model needed
     if (!out)
         return fail(MANDEL_EINVAL, "out_base is NULL");
+    if (la.mode == MANDEL_PLAN_ORDERED && !la.order)
+        return fail(MANDEL_EINVAL, "ORDERED needs an order array");
+    if (la.mode == MANDEL_PLAN_LEARNED_LPT && !la.mlp)
+        return fail(MANDEL_EINVAL, "LEARNED_LPT needs model parameters");
     if (la.mode == MANDEL_PLAN_PROBE_LPT || la.mode == MANDEL_PLAN_LEARNED_LPT) {
         int rc = ensure_order_buffers(p, true);
         if (rc)

@@ -140,3 +140,11 @@ def test_tile_count_at_extreme_sizes():
     assert native.tile_count(1, big, 64, 8) == (big + 63) // 64
     assert native.tile_count(big, 1, 1, 2 ** 20) == (big + 2 ** 20 - 1) // 2 ** 20
     assert native.tile_count(46341, 46341, 64, 8) == 5793 * 725
+
+
+def test_empty_image_needs_no_order():
+    # an empty image is a no-op in every policy: no output buffer and no order array
+    sched = native.make_sched(policy="ordered")
+    assert _call(m=0, out=None, sched=sched) == native.OK
+    assert _call(n=0, out=None, sched=sched) == native.OK
+    assert _call(sched=sched) == native.EINVAL   # a real image still needs its order

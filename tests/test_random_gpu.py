@@ -81,7 +81,8 @@ def _launch_kw(rng, plan, params):
     return kw
 
 
-@pytest.mark.parametrize("seed", range(160))
+# 286: a plan with no tiles launched in ORDERED mode with an empty order (NULL pointer)
+@pytest.mark.parametrize("seed", list(range(160)) + [286])
 def test_random_batch_and_schedule(seed):
     rng = np.random.default_rng(9000 + seed)
     views = [_view(rng) for _ in range(int(rng.integers(1, 5)))]
