@@ -1,7 +1,6 @@
 """The output path on the host: the library's PPM writer against the oracle's
 byte layout (oracle/output.py) and a small independent reader of the Netpbm
 format, plus argument checks of the colouring entry point (no GPU needed)."""
-import ctypes
 
 import numpy as np
 import pytest
