@@ -179,25 +179,48 @@ def tail_analysis(torch, native, plan, out, params, cost, clock_khz, stream, las
             "finished_ms_after_queue_dry_max": float(((t[idx, 1] - st[5]) / clock_khz).max())}
 
 
+# Deferred-block length for the launches with periodicity detection (64-256 measure
+# alike on the 8192 x 8192 view; 1024, the default, finds cycles later).
+PERIOD_BLOCK_ITERS = 128
+
+
 def periodicity(torch, native, view, plan, out, sum_counts, headline_ms, clock_khz,
                 stream) -> dict:
-    """Time to the same image with exact periodicity detection (FCFS queue): lanes
-    whose FP64 state recurs bit for bit stop early with count max_iter.  Skipped
-    updates are reported, not counted as executed."""
+    """Time to the same image with exact periodicity detection: lanes whose FP64
+    state recurs bit for bit stop early with count max_iter.  Skipped updates are
+    reported, not counted as executed.  Timed on the headline plan (FCFS queue,
+    blocks of up to 1024 updates), and on a plan whose blocks stop at 128 updates
+    (a cycle is found at the end of the first block that starts on it, so shorter
+    blocks find it sooner), with and without row stealing (the tiles whose orbits
+    never settle are the tail; stealing spreads their rows over idle wavefronts)."""
     ref = out.clone()
-    ms = timed_ms(torch, lambda: plan.launch(out, periodicity=1, use_graph=True, stream=stream),
-                  3, "periodicity detection")
-    assert torch.equal(out, ref), "periodicity detection changed the counts"
-    stats = torch.zeros(8, dtype=torch.int64, device="cuda")
-    plan.launch(out, periodicity=1, stats=stats, stream=stream)
-    torch.cuda.synchronize()
-    st = [int(v) for v in stats.cpu().tolist()]
-    executed = sum_counts - st[7]
-    return {"ms": ms, "sum_counts": sum_counts, "updates_skipped": st[7],
-            "updates_executed": executed,
-            "executed_pixel_iterations_per_s": executed / (ms / 1e3),
-            "time_to_image_speedup_vs_step": headline_ms / ms,
-            "tail": tail_fraction(st, clock_khz)}
+    short = native.Plan([view], {"block_iters": PERIOD_BLOCK_ITERS})
+
+    def run(p, steal, stats=None, graph=True):
+        p.launch(out, periodicity=1, use_graph=graph, steal=steal, stats=stats, stream=stream)
+
+    res = {}
+    for name, p, steal in (("blocks_1024_fcfs", plan, 0),
+                           (f"blocks_{PERIOD_BLOCK_ITERS}_fcfs", short, 0),
+                           (f"blocks_{PERIOD_BLOCK_ITERS}_fcfs_row_stealing", short, 1)):
+        ms = timed_ms(torch, lambda: run(p, steal), 3, f"periodicity detection {name}")
+        assert torch.equal(out, ref), f"periodicity detection changed the counts ({name})"
+        stats = torch.zeros(8, dtype=torch.int64, device="cuda")
+        out.fill_(-1)
+        run(p, steal, stats, graph=False)
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref), f"periodicity detection changed the counts ({name})"
+        st = [int(v) for v in stats.cpu().tolist()]
+        executed = sum_counts - st[7]
+        res[name] = {"ms": ms, "updates_skipped": st[7], "updates_executed": executed,
+                     "executed_pixel_iterations_per_s": executed / (ms / 1e3),
+                     "time_to_image_speedup_vs_step": headline_ms / ms,
+                     "tail": tail_fraction(st, clock_khz)}
+    short.close()
+    best = res[f"blocks_{PERIOD_BLOCK_ITERS}_fcfs_row_stealing"]
+    return dict(best, sum_counts=sum_counts,
+                configuration=f"plan block_iters {PERIOD_BLOCK_ITERS}, FCFS queue, row stealing",
+                variants=res)
 
 
 def output_path(torch, native, out, view, step, stream) -> dict:

@@ -161,3 +161,41 @@ def test_full_view_8192():
     idx = rng.integers(0, v.pixels, 2000)
     want = oracle.render_pixels(v.window, v.m, v.n, v.max_iter, v.R, idx, threads=16)
     assert np.array_equal(got.view(-1)[torch.tensor(idx, device="cuda")].cpu().numpy(), want)
+
+
+def test_bench_configuration_8192_short_blocks_stealing():
+    # The launch the benchmark times for detection: the 8192 x 8192 view on a plan
+    # whose deferred blocks stop at 128 updates, FCFS queue, row stealing, replayed
+    # from the graph.  Every pixel against the oracle's whole image (stored digest)
+    # and against the render without detection; detection must skip more updates
+    # than with the default 1024-update blocks.
+    import hashlib
+    import json
+    import os
+    v = workloads.c2()
+    plain = native.render(v.window, v.m, v.n, v.max_iter, v.R)
+    skipped = {}
+    for K, steal in ((1024, 0), (128, 1)):
+        plan = native.Plan([v], {"block_iters": K})
+        out = torch.full((plan.out_size(),), -1, dtype=torch.int32, device="cuda")
+        for _ in range(2):
+            out.fill_(-1)
+            plan.launch(out, periodicity=1, steal=steal, use_graph=True)
+            torch.cuda.synchronize()
+            assert torch.equal(out.view(v.m, v.n), plain), (K, steal)
+        stats = torch.zeros(8, dtype=torch.int64, device="cuda")
+        plan.launch(out, periodicity=1, steal=steal, stats=stats)
+        torch.cuda.synchronize()
+        assert torch.equal(out.view(v.m, v.n), plain), (K, steal)
+        st = stats.cpu().tolist()
+        skipped[K] = st[7]
+        _log(f"c2 periodic, blocks {K}, steal {steal}: skipped {st[7]}")
+        plan.close()
+    assert skipped[128] > skipped[1024] > 0
+    gold = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                        "oracle_digests.json")
+    g = json.load(open(gold))["c2"][0]
+    img = plain.cpu()
+    assert int(img.sum(dtype=torch.int64)) == g["sum"]
+    assert hashlib.sha256(np.ascontiguousarray(img.numpy(), dtype="<i4").tobytes()
+                          ).hexdigest() == g["sha256"]
