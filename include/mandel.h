@@ -203,8 +203,11 @@ typedef struct mandel_sched {
                                 short blocks (block_iters 64..256) find cycles
                                 sooner: on the 8192 x 8192 view at max_iter 10000
                                 they take 5.3 ms instead of 7.4 ms at 1024, and
-                                4.2 ms with row stealing.  Counts are unchanged;
-                                stats[7] adds the updates skipped.  0: off [0] */
+                                4.2 ms with row stealing.  Zooms centred on the
+                                boundary gain little (their orbits rarely settle
+                                on a short cycle): there short blocks only add
+                                their overhead.  Counts are unchanged; stats[7]
+                                adds the updates skipped.  0: off [0] */
     int64_t first_slot;      /* FCFS / ORDERED: the queue starts at this slot (slot
                                 q renders row part q mod tile_parts of tile q div
                                 tile_parts, through `order` for ORDERED); earlier
