@@ -34,6 +34,10 @@ def main(argv=None) -> int:
     ap.add_argument("--workers", type=int, default=0, help="workgroups for row schedules")
     ap.add_argument("--periodicity", action="store_true",
                     help="exact periodicity detection (same image, less work)")
+    ap.add_argument("--block-iters", type=int, default=0,
+                    help="longest block of untested updates (default 1024, and 128 with "
+                         "--periodicity: a cycle is found one block after the orbit reaches "
+                         "it, so shorter blocks find it sooner)")
     ap.add_argument("--double-double", action="store_true",
                     help="double-double arithmetic for pitches below binary64 resolution")
     ap.add_argument("--out", default="mandelbrot.ppm")
@@ -66,7 +70,8 @@ def main(argv=None) -> int:
         native.render_dd((cx, 0.0, cy, 0.0, dx, dy), m, n, args.max_iter, args.radius, out=out,
                          stats=stats)
     else:
-        kw = {"policy": args.schedule, "periodicity": int(args.periodicity), "stats": stats}
+        kw = {"policy": args.schedule, "periodicity": int(args.periodicity), "stats": stats,
+              "block_iters": args.block_iters or (128 if args.periodicity else 1024)}
         if args.schedule != "fcfs":
             kw["workers"] = args.workers
         native.render_sched((cx, cy, dx, dy), m, n, args.max_iter, args.radius, out=out, **kw)

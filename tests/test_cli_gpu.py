@@ -15,7 +15,8 @@ pytestmark = pytest.mark.gpu
 
 
 @pytest.mark.parametrize("extra", [[], ["--schedule", "static", "--workers", "7"],
-                                   ["--schedule", "alternating"], ["--periodicity"]])
+                                   ["--schedule", "alternating"], ["--periodicity"],
+                                   ["--periodicity", "--block-iters", "7"]])
 def test_cli_binary64(tmp_path, capsys, extra):
     path = tmp_path / "img.ppm"
     assert cli.main(["--size", "60", "80", "--max-iter", "400", "--out", str(path)] + extra) == 0
