@@ -270,8 +270,10 @@ def output_path(torch, native, out, view, step, stream) -> dict:
             "zoom_sequence_8x4096sq": seq}
 
 
-# FP64 instructions of one double-double update + test: 72 add/sub, 5 mul, 7 fma
-DD_INSTR_PER_ITER = 84
+# FP64 instructions of one double-double update + test as the kernel issues them: 66
+# add/sub, 3 mul, 13 fma (the two doublings of mul(X, Y) ride on fma's); the flops of
+# the arithmetic as defined: 72 add/sub, 5 mul, 7 fma
+DD_INSTR_PER_ITER = 82
 DD_FLOPS_PER_ITER = 72 + 5 + 2 * 7
 
 
