@@ -11,6 +11,7 @@ the paper reports for each run, Sec. IV).
 The window is given by its bounds (re_min re_max im_min im_max) or by its centre and
 pixel pitch.  --schedule picks the work partition: fcfs (device queue, default),
 static or alternating rows over --workers workgroups (paper Sec. III-A, III-C).
+With --periodicity the FCFS render runs from a one-view plan with row stealing.
 """
 from __future__ import annotations
 
@@ -63,10 +64,18 @@ def main(argv=None) -> int:
     stats = torch.zeros(8, dtype=torch.int64, device="cuda")
     a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     native.lib()
-    torch.cuda.synchronize()  # device and library set-up stay outside the timed part
+    plan = None
+    if args.periodicity and args.schedule == "fcfs":
+        # a one-view plan, for row stealing: the tiles whose orbits never settle on a
+        # short cycle are the tail, and stealing spreads their rows over idle wavefronts
+        plan = native.Plan([workloads.View((cx, cy, dx, dy), m, n, args.max_iter, args.radius)],
+                           {"block_iters": args.block_iters or 128})
+    torch.cuda.synchronize()  # device, library and plan set-up stay outside the timed part
     t0 = time.perf_counter()
     a.record()
-    if args.double_double:
+    if plan is not None:
+        plan.launch(out.view(-1), periodicity=1, steal=1, stats=stats)
+    elif args.double_double:
         native.render_dd((cx, 0.0, cy, 0.0, dx, dy), m, n, args.max_iter, args.radius, out=out,
                          stats=stats)
     else:
@@ -80,6 +89,8 @@ def main(argv=None) -> int:
     host = rgb.cpu()
     native.write_ppm(args.out, host, m, n)
     total = time.perf_counter() - t0
+    if plan is not None:
+        plan.close()
     counts = int(out.sum(dtype=torch.int64).item())
     skipped = 0 if args.double_double else int(stats[7].item())
     compute_ms = a.elapsed_time(b)
