@@ -451,8 +451,9 @@ int mandel_render_dd(const mandel_window_dd *w, int32_t m, int32_t n, int32_t ma
     a.max_iter = max_iter;
     a.tile_w = 64;
     a.tile_h = 8;
-    a.tiles_x = (n + 63) / 64;
-    a.ntiles = (int64_t)a.tiles_x * ((m + 7) / 8);
+    // in 64 bits: n + 63 overflows int32 for n near 2^31 (m = 1 is allowed there)
+    a.tiles_x = (int32_t)(((int64_t)n + 63) / 64);
+    a.ntiles = tile_count(m, n, 64, 8);
     a.out = out;
     a.head = head;
     a.stats = stats;

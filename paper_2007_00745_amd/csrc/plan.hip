@@ -154,31 +154,42 @@ int render_grid(mandel_plan *p, const mandel_launch &la, mandel_sched *sc, dim3 
     return tile_grid(*sc, true, p->ntiles, grid, block);
 }
 
-// Row counters (one per tile) and the held-tile table (one entry per wavefront of
-// the launch la will make), grown as needed.
-int ensure_steal_buffers(mandel_plan *p, const mandel_launch &la)
+// Row counters (one per tile) and the held-tile table (one entry per wavefront).  The
+// table is sized once, at first use, for the largest launch any queue mode of this plan
+// can make (FCFS or ordered, with or without periodicity detection: their resident
+// group counts differ), so captured graphs, which hold its address and clear length,
+// never see it reallocated.
+int ensure_steal_buffers(mandel_plan *p)
 {
-    mandel_sched sc;
-    dim3 grid, block;
-    int rc = render_grid(p, la, &sc, &grid, &block);
-    if (rc)
-        return rc;
-    const int64_t waves = (int64_t)grid.x * (block.x / 64);
     hipError_t e;
     if (!p->d_chunk) {
         e = hipMalloc((void **)&p->d_chunk, sizeof(int32_t) * (size_t)p->ntiles);
         if (e != hipSuccess)
             return fail(MANDEL_ENOMEM, "hipMalloc(row counters): %s", hipGetErrorString(e));
     }
-    if (p->active_len < waves) {
-        (void)hipFree(p->d_active);
-        p->d_active = nullptr;
-        p->active_len = 0;
-        e = hipMalloc((void **)&p->d_active, sizeof(int32_t) * (size_t)waves);
-        if (e != hipSuccess)
-            return fail(MANDEL_ENOMEM, "hipMalloc(held tiles): %s", hipGetErrorString(e));
-        p->active_len = waves;
+    if (p->d_active)
+        return MANDEL_OK;
+    int64_t waves = 0;
+    const int32_t modes[2] = {MANDEL_PLAN_FCFS, MANDEL_PLAN_ORDERED};
+    for (int32_t mode : modes) {
+        for (int32_t per = 0; per <= 1; ++per) {
+            mandel_launch la;
+            std::memset(&la, 0, sizeof la);
+            la.mode = mode;
+            la.periodicity = per;
+            mandel_sched sc;
+            dim3 grid, block;
+            int rc = render_grid(p, la, &sc, &grid, &block);
+            if (rc)
+                return rc;
+            const int64_t w = (int64_t)grid.x * (block.x / 64);
+            waves = w > waves ? w : waves;
+        }
     }
+    e = hipMalloc((void **)&p->d_active, sizeof(int32_t) * (size_t)waves);
+    if (e != hipSuccess)
+        return fail(MANDEL_ENOMEM, "hipMalloc(held tiles): %s", hipGetErrorString(e));
+    p->active_len = waves;
     return MANDEL_OK;
 }
 
@@ -391,7 +402,7 @@ int mandel_plan_launch(mandel_plan *p, int32_t *out, const mandel_launch *args, 
             return rc;
     }
     if (la.steal) {
-        int rc = ensure_steal_buffers(p, la);
+        int rc = ensure_steal_buffers(p);
         if (rc)
             return rc;
     }
