@@ -13,6 +13,7 @@ import torch
 
 import oracle
 from oracle import mlp as mlp_ref
+from oracle import order as order_ref
 from paper_2007_00745_amd import native, workloads
 
 pytestmark = pytest.mark.gpu
@@ -38,13 +39,21 @@ def _check(plan, out, want):
         assert np.array_equal(g.numpy(), w), f"view {k}"
 
 
-def _params(seed, feat=None):
+def _params(seed, feat=None, biases=True):
+    # He-uniform weights; with biases=True every bias is drawn non-zero as well, so
+    # that the kernels' bias reads are compared with the reference too
     rng = np.random.default_rng(seed)
     if feat is not None:
         f = feat.cpu().double().numpy()
         p = mlp_ref.init_params(rng, mu=f.mean(0), sd=f.std(0) + 1e-3)
     else:
         p = mlp_ref.init_params(rng, mu=rng.normal(size=68) * 0.1, sd=rng.uniform(0.5, 2, 68))
+    if biases:
+        d = mlp_ref.unpack(p)
+        d["b1"] = rng.normal(size=64) * 0.5
+        d["b2"] = rng.normal(size=64) * 0.5
+        d["b3"] = rng.normal(size=1) + 3.0
+        p = mlp_ref.pack(d)
     return p
 
 
@@ -303,15 +312,44 @@ def test_features_probe_counts(small_batch):
     plan.close()
 
 
-def test_mlp_forward_matches_fp64():
-    rng = np.random.default_rng(11)
-    p = _params(12)
-    x = rng.normal(size=(3001, 68)) * rng.uniform(0.5, 3, 68) + rng.normal(size=68)
-    y_ref = mlp_ref.forward(p, x)
-    y = native.mlp_forward(torch.tensor(p, dtype=torch.float32, device="cuda"),
-                           torch.tensor(x, dtype=torch.float32, device="cuda"))
+def _forward_close(p, x):
+    # the FP32 kernel against the FP64 reference, evaluated at the FP32-rounded
+    # parameters and inputs the kernel sees
+    p32, x32 = np.float32(p), np.float32(x)
+    y_ref = mlp_ref.forward(p32.astype(np.float64), x32.astype(np.float64))
+    y = native.mlp_forward(torch.tensor(p32, device="cuda"), torch.tensor(x32, device="cuda"))
     torch.cuda.synchronize()
-    assert np.allclose(y.cpu().numpy(), y_ref, rtol=1e-3, atol=1e-4 * np.abs(y_ref).max())
+    y = y.cpu().numpy()
+    assert np.allclose(y, y_ref, rtol=1e-3, atol=1e-4 * np.abs(y_ref).max()), \
+        float(np.abs(y - y_ref).max())
+    return y, y_ref
+
+
+@pytest.mark.parametrize("biases", [False, True])
+def test_mlp_forward_matches_fp64(biases):
+    rng = np.random.default_rng(11)
+    p = _params(12, biases=biases)
+    x = rng.normal(size=(3001, 68)) * rng.uniform(0.5, 3, 68) + rng.normal(size=68)
+    y, y_ref = _forward_close(p, x)
+    if biases:
+        # the biases move the output: a kernel that ignored them would be far off
+        y0 = mlp_ref.forward(_params(12, biases=False), x)
+        assert np.abs(y_ref - y0).max() > 100 * np.abs(y - y_ref).max()
+
+
+def test_mlp_forward_trained_params():
+    # inference on a parameter vector trained by the GPU's own training step (every
+    # weight and bias moved away from its initial value) and on real tile features
+    from paper_2007_00745_amd import costmodel
+    views = workloads.training_views(range(1000, 1002), per_seed=8, lo=64, hi=512)
+    feat, target, _, plan = costmodel.collect(views)
+    params, losses = costmodel.train(feat, target, epochs=3, batch=256, lr=1e-3, seed=1)
+    _log(f"trained on {feat.shape[0]} tiles, losses {[round(x, 3) for x in losses]}")
+    p = params.cpu().double().numpy()
+    d = mlp_ref.unpack(p)
+    assert all(np.abs(d[b]).max() > 0 for b in ("b1", "b2", "b3"))
+    _forward_close(p, feat.cpu().double().numpy())
+    plan.close()
 
 
 def test_mlp_train_step_matches_fp64():
@@ -353,26 +391,36 @@ def test_mlp_train_step_matches_fp64():
         assert np.allclose(P.cpu().double().numpy()[big], pr[big], rtol=1e-4, atol=1e-6)
 
 
-def test_order_desc():
-    rng = np.random.default_rng(31)
-    for n in (1, 2, 1000, 131072, 2_621_440):
-        keys = rng.uniform(-3, 52, n).astype(np.float32)
-        if n > 10:
-            keys[rng.choice(n, 5, replace=False)] = np.nan
-        k = torch.tensor(keys, device="cuda")
-        perm = native.order_desc(k)
-        torch.cuda.synchronize()
-        pm = perm.cpu().numpy()
-        assert np.array_equal(np.sort(pm), np.arange(n))
-        kk = keys[pm]
-        nb = native.ORDER_BUCKETS
-        f32 = np.float32   # the kernel's bucket arithmetic, in float32
-        scale = f32(nb - 1) / (f32(native.ORDER_KEY_HI) - f32(native.ORDER_KEY_LO))
-        u = (f32(native.ORDER_KEY_HI) - kk) * scale
-        b = np.where(np.isnan(kk), nb - 1, np.floor(np.clip(np.nan_to_num(u, nan=0), 0, nb - 2)))
-        assert np.all(np.diff(b) >= 0)
-        if n > 10:
-            assert np.all(np.isnan(kk[-5:]))
+def test_order_constants_match_the_reference():
+    assert native.ORDER_BUCKETS == order_ref.BUCKETS
+    assert np.float32(native.ORDER_KEY_LO) == order_ref.KEY_LO
+    assert np.float32(native.ORDER_KEY_HI) == order_ref.KEY_HI
+
+
+_EDGE_KEYS = np.array([50.0, -2.0, 50.5, -2.5, 1e30, -1e30, np.inf, -np.inf, np.nan, 0.0, -0.0,
+                       24.0, np.nextafter(np.float32(50), np.float32(0)),
+                       np.nextafter(np.float32(-2), np.float32(0)), 1.0 / 78.75],
+                      dtype=np.float32)
+
+
+@pytest.mark.parametrize("n", [0, 1, 2, 15, 1000, 131072, 2_621_440])
+def test_order_desc(n):
+    # the device order visits exactly the bucket sequence of the reference
+    # (oracle/order.py), and is a permutation; within a bucket any order is valid
+    rng = np.random.default_rng(31 + n)
+    keys = rng.uniform(-3, 52, n).astype(np.float32)
+    if n >= 15:
+        keys[rng.choice(n, 15, replace=False)] = _EDGE_KEYS
+    if n > 1000:
+        keys[rng.choice(n, n // 3, replace=False)] = np.float32(7.25)   # one crowded bucket
+    k = torch.tensor(keys, device="cuda")
+    perm = native.order_desc(k)
+    torch.cuda.synchronize()
+    pm = perm.cpu().numpy().astype(np.int64)
+    assert pm.shape == (n,)
+    assert np.array_equal(np.sort(pm), np.arange(n))
+    assert np.array_equal(order_ref.bucket(keys[pm]), order_ref.bucket_sequence(keys))
+    assert order_ref.is_valid_order(keys, pm)
 
 
 def test_fp64_probe_runs():
