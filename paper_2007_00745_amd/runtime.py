@@ -3,9 +3,12 @@ a stream watchdog.
 
 * ``autotune_cached(views, path)`` -- the library caches autotune results per
   device and batch signature for the life of the process; this keeps them in a
-  JSON file across processes, keyed by the device name and the batch signature
-  (sizes, max_iter and radius of every view, sorted), so a batch seen before is
-  not re-timed.
+  JSON file across processes, keyed by the device name, the sample size and the
+  batch signature, so a batch seen before is not re-timed.  The signature covers
+  every field the library's own cache key is computed from (size, max_iter,
+  radius and window of every view, in submission order), so two batches that
+  share a file entry would also share the library's entry: zoom and position
+  change where the work sits, so a tuning is never reused across them.
 * ``wait(stream, timeout)`` -- polls a stream until its work is done or the time
   runs out (then raises TimeoutError, leaving the work running): a host watchdog
   for callers that must not block forever on a device call.
@@ -21,9 +24,10 @@ import time
 from . import native
 
 
-def batch_signature(views) -> str:
-    items = sorted((v.m, v.n, v.max_iter, float(v.R).hex()) for v in views)
-    return hashlib.sha256(json.dumps(items).encode()).hexdigest()[:24]
+def batch_signature(views, max_sample: int = 8) -> str:
+    items = [(v.m, v.n, v.max_iter, float(v.R).hex(), [float(x).hex() for x in v.window])
+             for v in views]
+    return hashlib.sha256(json.dumps([max_sample, items]).encode()).hexdigest()[:24]
 
 
 def _read_table(path: str) -> dict:
@@ -41,7 +45,7 @@ def autotune_cached(views, path: str, max_sample: int = 8, device_name: str | No
     if device_name is None:
         import torch
         device_name = torch.cuda.get_device_name()
-    key = f"{device_name}|{batch_signature(views)}"
+    key = f"{device_name}|{batch_signature(views, max_sample)}"
     table = _read_table(path)
     if key in table:
         return dict(table[key]), True

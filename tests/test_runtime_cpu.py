@@ -23,12 +23,24 @@ def test_watchdog_returns_and_times_out():
         runtime.wait(_FakeStream(10 ** 9), timeout=0.02, poll=1e-3)
 
 
-def test_signature_ignores_order_and_window():
-    a = [workloads.View((0.0, 0.0, 1e-3, 1e-3), 10, 20, 100), workloads.c1()]
-    b = [workloads.c1(), workloads.View((0.5, 0.1, 1e-4, 1e-4), 10, 20, 100)]
-    assert runtime.batch_signature(a) == runtime.batch_signature(b)
-    c = [workloads.c1(), workloads.View((0.0, 0.0, 1e-3, 1e-3), 10, 20, 101)]
-    assert runtime.batch_signature(a) != runtime.batch_signature(c)
+def test_signature_keys_every_field_the_library_keys():
+    # the file cache keys on what the library's in-process cache keys on (size,
+    # max_iter, radius and window of the views, in order) and on the sample size, so
+    # the two caches cannot hand out a tuning for different batches
+    v1 = workloads.View((0.0, 0.0, 1e-3, 1e-3), 10, 20, 100)
+    a = [v1, workloads.c1()]
+    assert runtime.batch_signature(a) == runtime.batch_signature(list(a))
+    variants = [
+        [workloads.View((0.5, 0.0, 1e-3, 1e-3), 10, 20, 100), workloads.c1()],   # centre
+        [workloads.View((0.0, 0.0, 1e-4, 1e-3), 10, 20, 100), workloads.c1()],   # zoom
+        [workloads.View((0.0, 0.0, 1e-3, 1e-3), 10, 20, 101), workloads.c1()],   # max_iter
+        [workloads.View((0.0, 0.0, 1e-3, 1e-3), 10, 20, 100, 3.0), workloads.c1()],  # R
+        [workloads.View((0.0, 0.0, 1e-3, 1e-3), 11, 20, 100), workloads.c1()],   # rows
+        [workloads.c1(), v1],                                                     # order
+    ]
+    sigs = {runtime.batch_signature(b) for b in variants}
+    assert len(sigs) == len(variants) and runtime.batch_signature(a) not in sigs
+    assert runtime.batch_signature(a, 8) != runtime.batch_signature(a, 4)
 
 
 def test_autotune_cache_file(tmp_path, monkeypatch):
