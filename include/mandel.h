@@ -230,6 +230,23 @@ typedef struct mandel_sched {
 int mandel_render_sched(const mandel_window *w, int32_t m, int32_t n, int32_t max_iter,
                         double R, int32_t *out, const mandel_sched *s, void *stream);
 
+/*
+ * mandel_render_sched_noalloc -- mandel_render_sched for callers that cannot
+ * allocate device memory (code under stream or graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc).  Same arguments, checks, results and
+ * error codes; it calls no hipMalloc, hipFree or allocating routine.  Its only
+ * scratch is the queue head: one 64-bit counter in a 256-byte file-scope device
+ * array that every GPU holds once, from the first call on that GPU until the
+ * process ends.  That is the whole of its scratch for any image size, so no size
+ * is refused for want of scratch (the image limits are mandel_render_sched's).
+ * All calls on one GPU share the array, and each call resets the head before its
+ * render: calls that overlap in time on one GPU (different streams without
+ * synchronisation between them) race and must not be issued; calls in order on
+ * one stream are fine.
+ */
+int mandel_render_sched_noalloc(const mandel_window *w, int32_t m, int32_t n, int32_t max_iter,
+                                double R, int32_t *out, const mandel_sched *s, void *stream);
+
 /* Number of tiles of an m x n view under a tile shape (0 for an empty view). */
 int64_t mandel_tile_count(int32_t m, int32_t n, int32_t tile_w, int32_t tile_h);
 

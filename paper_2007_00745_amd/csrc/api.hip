@@ -87,6 +87,41 @@ int workspace_order(void *stream, uint32_t **hist)
     return MANDEL_OK;
 }
 
+// ---- allocation-free variant: the queue head in a file-scope device array ----
+// mandel_render_sched_noalloc takes its queue head from `scratch` instead of a
+// hipMalloc'd workspace.  Each device holds its own copy of the array, at its own
+// address, until the process ends.  In host code the name `scratch` is only a
+// host-side stand-in, so host code uses nothing but the device address that
+// hipGetSymbolAddress returns, looked up once per device with that device current.
+constexpr int NOALLOC_SCRATCH_BYTES = HEAD_BYTES;
+static __device__ __align__(256) unsigned long long scratch[NOALLOC_SCRATCH_BYTES / 8];
+
+namespace {
+std::mutex g_scratch_mu;
+std::map<int, unsigned long long *> g_scratch; // device -> address of its scratch
+} // namespace
+
+int scratch_head(unsigned long long **head)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return hip_fail(e, "hipGetDevice");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch.find(dev);
+    if (it == g_scratch.end()) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess)
+            return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        if (!p)
+            return fail(MANDEL_EHIP, "hipGetSymbolAddress(scratch) returned NULL");
+        it = g_scratch.emplace(dev, (unsigned long long *)p).first;
+    }
+    *head = it->second;
+    return MANDEL_OK;
+}
+
 int device_cus(int *cus)
 {
     int dev = 0;
@@ -291,8 +326,8 @@ int64_t mandel_tile_count(int32_t m, int32_t n, int32_t tile_w, int32_t tile_h)
     return tile_count(m, n, tile_w, tile_h);
 }
 
-int mandel_render_sched(const mandel_window *w, int32_t m, int32_t n, int32_t max_iter,
-                        double R, int32_t *out, const mandel_sched *sp, void *stream)
+static int render_sched(const mandel_window *w, int32_t m, int32_t n, int32_t max_iter, double R,
+                        int32_t *out, const mandel_sched *sp, void *stream, bool noalloc)
 {
     clear_error();
     mandel_sched s;
@@ -337,7 +372,7 @@ int mandel_render_sched(const mandel_window *w, int32_t m, int32_t n, int32_t ma
     a.stats = s.stats;
 
     unsigned long long *head = nullptr;
-    rc = workspace_head(st, &head);
+    rc = noalloc ? scratch_head(&head) : workspace_head(st, &head);
     if (rc)
         return rc;
     a.head = head;
@@ -360,6 +395,18 @@ int mandel_render_sched(const mandel_window *w, int32_t m, int32_t n, int32_t ma
     if (e != hipSuccess)
         return hip_fail(e, "render launch");
     return MANDEL_OK;
+}
+
+int mandel_render_sched(const mandel_window *w, int32_t m, int32_t n, int32_t max_iter,
+                        double R, int32_t *out, const mandel_sched *sp, void *stream)
+{
+    return render_sched(w, m, n, max_iter, R, out, sp, stream, false);
+}
+
+int mandel_render_sched_noalloc(const mandel_window *w, int32_t m, int32_t n, int32_t max_iter,
+                                double R, int32_t *out, const mandel_sched *sp, void *stream)
+{
+    return render_sched(w, m, n, max_iter, R, out, sp, stream, true);
 }
 
 int mandel_render(const mandel_window *w, int32_t m, int32_t n, int32_t max_iter, double R,

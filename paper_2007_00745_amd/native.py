@@ -120,6 +120,9 @@ def lib() -> ctypes.CDLL:
         L.mandel_render_sched.argtypes = [ctypes.POINTER(Window), i32, i32, i32, d, P,
                                           ctypes.POINTER(Sched), P]
         L.mandel_render_sched.restype = ctypes.c_int
+        L.mandel_render_sched_noalloc.argtypes = [ctypes.POINTER(Window), i32, i32, i32, d, P,
+                                                  ctypes.POINTER(Sched), P]
+        L.mandel_render_sched_noalloc.restype = ctypes.c_int
         L.mandel_tile_count.argtypes = [i32, i32, i32, i32]
         L.mandel_tile_count.restype = i64
         L.mandel_last_error.argtypes = []
@@ -286,9 +289,11 @@ def make_sched(policy="fcfs", tile_w=0, tile_h=0, grain=0, workers=0, waves_per_
 
 
 def render_sched(window, m: int, n: int, max_iter: int, R: float, out=None, stream=None,
-                 **sched):
+                 noalloc: bool = False, **sched):
     """mandel_render_sched with the schedule fields of mandel_sched as keywords.  The
-    optional buffers are checked against the sizes this call implies."""
+    optional buffers are checked against the sizes this call implies.  noalloc=True
+    calls mandel_render_sched_noalloc instead (queue head in the library's static
+    device scratch; calls that overlap in time on one GPU race)."""
     out = _out(out, m, n)
     pol = sched.get("policy", "fcfs")
     pol = POLICIES[pol] if isinstance(pol, str) else int(pol)
@@ -303,8 +308,9 @@ def render_sched(window, m: int, n: int, max_iter: int, R: float, out=None, stre
             _dev(sched[key], dt, size, key)
     s = make_sched(**sched)
     w = Window(*[float(v) for v in window])
-    check(lib().mandel_render_sched(ctypes.byref(w), m, n, int(max_iter), float(R), _ptr(out),
-                                    ctypes.byref(s), _stream(stream)))
+    fn = lib().mandel_render_sched_noalloc if noalloc else lib().mandel_render_sched
+    check(fn(ctypes.byref(w), m, n, int(max_iter), float(R), _ptr(out), ctypes.byref(s),
+             _stream(stream)))
     return out
 
 

@@ -51,6 +51,23 @@ def test_invalid_arguments(kw):
     assert native.lib().mandel_last_error()
 
 
+@pytest.mark.parametrize("kw", [
+    dict(m=-1), dict(mi=0), dict(R=float("nan")), dict(win=(0.0, 0.0, 0.0, 0.01)),
+    dict(m=1 << 20, n=1 << 20), dict(out=None),
+])
+def test_noalloc_invalid_arguments(kw):
+    # the allocation-free variant checks its arguments as mandel_render_sched does,
+    # before it looks up its device scratch
+    L = native.lib()
+    a = dict(win=(-0.5, 0.0, 0.01, 0.01), m=8, n=8, mi=10, R=2.0, out=0x1000)
+    a.update(kw)
+    w = native.Window(*a["win"])
+    s = native.make_sched()
+    assert L.mandel_render_sched_noalloc(ctypes.byref(w), a["m"], a["n"], a["mi"], a["R"],
+                                         a["out"], ctypes.byref(s), None) == native.EINVAL
+    assert native.lib().mandel_last_error()
+
+
 def test_null_pointers():
     L = native.lib()
     assert L.mandel_render(None, 8, 8, 10, 2.0, 0x1000, None) == native.EINVAL
