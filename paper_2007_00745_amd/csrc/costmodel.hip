@@ -48,6 +48,9 @@ __device__ __forceinline__ int32_t find_view_b(ConstViewDesc *views, int32_t nvi
 }
 
 // ---- probe features: one wavefront per tile, one probe pixel per lane ------
+constexpr int32_t PROBE_BLOCK = 8;   // updates per untested block
+constexpr int32_t PROBE_REPLAYS = 2; // replays before a wave tests every update
+
 __global__ void __launch_bounds__(256) features_kernel(const ViewDesc *views, int32_t nviews,
                                                        int64_t ntiles, int32_t tile_w,
                                                        int32_t tile_h, int32_t probe_cap,
@@ -79,46 +82,62 @@ __global__ void __launch_bounds__(256) features_kernel(const ViewDesc *views, in
     const double cx = vd.cx0 + px;
     const double cy = vd.cy0 + py;
     const int32_t cap = vd.max_iter < probe_cap ? vd.max_iter : probe_cap;
-    // min(count, cap): test z_{k-1} before forming z_k, reusing its squares; the
-    // test of z_cap is not needed because the count is capped at cap anyway.  Four
-    // tested updates per round without branches; a lane that escaped keeps its
-    // count and its (unused) state runs on; the wave stops when no lane is live.
+    // min(count, cap) needs the tests of z_1 .. z_{cap-1} only: count >= cap gives cap.
+    // The wave advances in blocks of up to PROBE_BLOCK updates.  While no lane has
+    // escaped and every lane's |c| lies in the disk where an escaped orbit keeps
+    // growing (the render's deferred-test condition), a block runs untested and one
+    // test of its last state tells whether any of its states escaped.  If one did, the
+    // whole wave returns to the block's first state and replays it with a test after
+    // every update, which finds the first escape exactly.  After PROBE_REPLAYS replays
+    // the wave tests every update until it is done.
     const double R2 = vd.R2;
+    const bool safe = cx * cx + cy * cy <= vd.safe2;
     double x = 0.0, y = 0.0;
     int32_t cnt = cap;
     bool live = true;
-    auto tested = [&](int32_t it) { // test z_{it-1}, then form z_it
+    int32_t replays = __builtin_amdgcn_ballot_w64(!safe) != 0 ? PROBE_REPLAYS : 0;
+    auto update = [&]() {
         const double xx = x * x;
         const double yy = y * y;
-        const bool esc = live && xx + yy > R2;
-        cnt = esc ? it - 1 : cnt;
-        live = live && !esc;
         const double tt = x * y;
         x = (xx - yy) + cx;
         y = __builtin_fma(2.0, tt, cy);
     };
-    int32_t it = 1;
-    bool any = true;
-    for (; it + 3 <= cap; it += 4) {
-        tested(it);
-        tested(it + 1);
-        tested(it + 2);
-        tested(it + 3);
-        if (__builtin_amdgcn_ballot_w64(live) == 0) {
-            any = false;
-            break;
+    for (int32_t it = 0; it < cap - 1;) { // z_it formed and tested in every live lane
+        const int32_t L = cap - 1 - it < PROBE_BLOCK ? cap - 1 - it : PROBE_BLOCK;
+        if (replays < PROBE_REPLAYS) {
+            const double xs = x, ys = y;
+            for (int32_t u = 0; u < L; ++u)
+                update();
+            const bool esc = live && !(x * x + y * y <= R2);
+            if (__builtin_amdgcn_ballot_w64(esc) == 0) {
+                it += L;
+                continue;
+            }
+            x = xs;
+            y = ys;
+            ++replays;
         }
+        for (int32_t u = 1; u <= L; ++u) { // form z_{it+u}, then test it
+            update();
+            const bool esc = live && x * x + y * y > R2;
+            cnt = esc ? it + u : cnt;
+            live = live && !esc;
+        }
+        it += L;
+        if (__builtin_amdgcn_ballot_w64(live) == 0)
+            break;
     }
-    for (; any && it <= cap; ++it)
-        tested(it);
     float *f = feat + t * NF;
     f[4 + lane] = logf(1.0f + (float)cnt) / logf(1.0f + (float)cap);
     if (lane < 4) {
         float val;
         if (lane == 0)
-            val = (float)(vd.cx0 + (((double)x0 + 0.5 * (double)w) - 0.5 * (double)vd.n) * vd.dx);
+            val = (float)(vd.cx0 +
+                          (((double)x0 + 0.5 * (double)w) - 0.5 * (double)vd.n) * vd.dx);
         else if (lane == 1)
-            val = (float)(vd.cy0 + (((double)y0 + 0.5 * (double)h) - 0.5 * (double)vd.m) * vd.dy);
+            val = (float)(vd.cy0 +
+                          (((double)y0 + 0.5 * (double)h) - 0.5 * (double)vd.m) * vd.dy);
         else if (lane == 2)
             val = log10f((float)((double)w * vd.dx));
         else
@@ -142,42 +161,108 @@ __global__ void probe_key_kernel(const float *feat, int64_t n, float probe_cap, 
     keys[t] = logf(1.0f + s);
 }
 
-// ---- MLP inference: one row per thread, parameters staged in LDS -----------
-// The cost model is FP32 and checked within tolerances, so its dot products use
-// fused multiply-add (fmaf) although the file is compiled without contraction.
+// ---- MLP inference on the matrix cores ---------------------------------------
+// The two hidden layers are dense contractions over 16-row blocks of tiles:
+//   H1[16 x 64] = relu(Xs[16 x 68] W1^T + b1),  H2[16 x 64] = relu(H1 W2^T + b2),
+// each computed as 4 column blocks of 16 with v_mfma_f32_16x16x4_f32 (FP32 inputs,
+// FP32 accumulation).  Operand layouts of that instruction (wave64): lane l holds
+// A[l % 16][l / 16] and B[l / 16][l % 16] of one K = 4 step, and the result
+// D[4 (l / 16) + r][l % 16] in accumulator register r.  H1 passes through LDS to
+// change from the result layout to the operand layout.  The output layer is a dot
+// product per row, summed over the 16 lanes that hold the row's columns.
+typedef float mf4 __attribute__((ext_vector_type(4)));
+
+constexpr int MLP_ROWS = 16;          // rows per wave and block step
+constexpr int MLP_WAVES = 4;          // wavefronts per workgroup
+constexpr int H_STRIDE = NH + 4;      // LDS row stride of H1 (bank spread)
+
 __global__ void __launch_bounds__(256) mlp_forward_kernel(const float *params, const float *x,
                                                           int64_t n, float *y)
 {
     __shared__ float P[MANDEL_MLP_PARAMS];
+    __shared__ float H[MLP_WAVES][MLP_ROWS * H_STRIDE];
     for (int q = threadIdx.x; q < MANDEL_MLP_PARAMS; q += blockDim.x)
         P[q] = params[q];
     __syncthreads();
-    const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (row >= n)
-        return;
-    const float *xr = x + row * NF;
-    float h[NH];
+    const int w = threadIdx.x >> 6;
+    const int l = threadIdx.x & 63;
+    const int lr = l & 15;  // operand row (A) / column (B, D) of this lane
+    const int lk = l >> 4;  // operand K index within a step (A, B); row group (D)
+    float *Hw = H[w];
+    const int64_t groups = (n + MLP_ROWS - 1) / MLP_ROWS;
+    for (int64_t g = (int64_t)blockIdx.x * MLP_WAVES + w; g < groups;
+         g += (int64_t)gridDim.x * MLP_WAVES) {
+        const int64_t row0 = g * MLP_ROWS;
+        const int64_t arow = row0 + lr;
+        const bool aok = arow < n;
+        const float *xr = x + (aok ? arow : 0) * NF;
+        // layer 1
+        mf4 acc[4];
 #pragma unroll
-    for (int o = 0; o < NH; ++o)
-        h[o] = P[OFF_B1 + o];
-    for (int i = 0; i < NF; ++i) {
-        const float xi = (xr[i] - P[OFF_MU + i]) * P[OFF_ISD + i];
+        for (int nb = 0; nb < 4; ++nb) {
+            const float b = P[OFF_B1 + 16 * nb + lr];
+            acc[nb] = mf4{b, b, b, b};
+        }
 #pragma unroll
-        for (int o = 0; o < NH; ++o)
-            h[o] = fmaf(P[OFF_W1 + o * NF + i], xi, h[o]);
+        for (int st = 0; st < NF / 4; ++st) {
+            const int k = 4 * st + lk;
+            const float a = aok ? (xr[k] - P[OFF_MU + k]) * P[OFF_ISD + k] : 0.0f;
+#pragma unroll
+            for (int nb = 0; nb < 4; ++nb)
+                acc[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+                    a, P[OFF_W1 + (16 * nb + lr) * NF + k], acc[nb], 0, 0, 0);
+        }
+#pragma unroll
+        for (int nb = 0; nb < 4; ++nb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                Hw[(4 * lk + r) * H_STRIDE + 16 * nb + lr] = fmaxf(acc[nb][r], 0.0f);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        // layer 2
+#pragma unroll
+        for (int nb = 0; nb < 4; ++nb) {
+            const float b = P[OFF_B2 + 16 * nb + lr];
+            acc[nb] = mf4{b, b, b, b};
+        }
+#pragma unroll
+        for (int st = 0; st < NH / 4; ++st) {
+            const int k = 4 * st + lk;
+            const float a = Hw[lr * H_STRIDE + k];
+#pragma unroll
+            for (int nb = 0; nb < 4; ++nb)
+                acc[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+                    a, P[OFF_W2 + (16 * nb + lr) * NH + k], acc[nb], 0, 0, 0);
+        }
+        // output layer: row 4 lk + r gets sum over columns j of w3[j] relu(H2[row][j])
+        float part[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            float s = 0.0f;
+#pragma unroll
+            for (int nb = 0; nb < 4; ++nb)
+                s = fmaf(P[OFF_W3 + 16 * nb + lr], fmaxf(acc[nb][r], 0.0f), s);
+            part[r] = s;
+        }
+#pragma unroll
+        for (int off = 8; off >= 1; off >>= 1)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                part[r] += __shfl_xor(part[r], off, 16);
+        if (lr == 0) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t row = row0 + 4 * lk + r;
+                if (row < n)
+                    y[row] = P[OFF_B3] + part[r];
+            }
+        }
+        // H1 of this block is read; the next block may overwrite it
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
-#pragma unroll
-    for (int o = 0; o < NH; ++o)
-        h[o] = fmaxf(h[o], 0.0f);
-    float out = P[OFF_B3];
-    for (int o = 0; o < NH; ++o) {
-        float a = P[OFF_B2 + o];
-#pragma unroll
-        for (int i = 0; i < NH; ++i)
-            a = fmaf(P[OFF_W2 + o * NH + i], h[i], a);
-        out = fmaf(P[OFF_W3 + o], fmaxf(a, 0.0f), out);
-    }
-    y[row] = out;
 }
 
 // ---- MLP training ------------------------------------------------------------
@@ -534,8 +619,15 @@ hipError_t launch_probe_key(const float *feat, int64_t n, int32_t probe_cap, flo
 hipError_t launch_mlp_forward(const float *params, const float *x, int64_t n, float *y,
                               hipStream_t s)
 {
-    hipLaunchKernelGGL(mlp_forward_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, params, x,
-                       n, y);
+    // each workgroup stages the parameters once and loops over 16-row blocks
+    const int64_t groups = (n + MLP_ROWS - 1) / MLP_ROWS;
+    int64_t blocks = (groups + MLP_WAVES - 1) / MLP_WAVES;
+    if (blocks > 2048)
+        blocks = 2048;
+    if (blocks < 1)
+        return hipSuccess;
+    hipLaunchKernelGGL(mlp_forward_kernel, dim3((unsigned)blocks), dim3(64 * MLP_WAVES), 0, s,
+                       params, x, n, y);
     return hipGetLastError();
 }
 
