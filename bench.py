@@ -100,25 +100,63 @@ def measured_traffic():
         return None
 
 
-def cpu_baseline(view, rows_step: int, threads: int) -> dict:
-    """The oracle (one single-threaded loop per worker) on every rows_step-th row."""
+def _oracle_rows(tasks, threads: int) -> tuple[int, float]:
+    """Runs the oracle on (view, rows) tasks: each task renders the given rows of one
+    view on one thread; `threads` workers take tasks first come first served (the
+    paper's dynamic scheme, Sec. III-B, on the host).  Returns (sum of counts, wall
+    seconds)."""
+    from concurrent.futures import ThreadPoolExecutor
+
     import numpy as np
 
     import oracle
-    rows = np.arange(0, view.m, rows_step)
-    idx = (rows[:, None] * view.n + np.arange(view.n)[None, :]).ravel()
+
+    def one(task):
+        v, rows = task
+        idx = (np.asarray(rows, dtype=np.int64)[:, None] * v.n +
+               np.arange(v.n, dtype=np.int64)[None, :]).ravel()
+        c = oracle.render_pixels(v.window, v.m, v.n, v.max_iter, v.R, idx, threads=1)
+        return int(c.sum(dtype=np.int64))
+
     t0 = time.perf_counter()
-    counts = oracle.render_pixels(view.window, view.m, view.n, view.max_iter, view.R, idx,
-                                  threads=threads)
-    dt = time.perf_counter() - t0
-    total = int(counts.sum(dtype=np.int64))
-    # one core on the small 640 x 480 view, whole image
+    if threads <= 1:
+        total = sum(one(t) for t in tasks)
+    else:
+        with ThreadPoolExecutor(max_workers=threads) as ex:
+            total = sum(ex.map(one, tasks))
+    return total, time.perf_counter() - t0
+
+
+def cpu_baseline(view, rows_step: int, threads: int) -> dict:
+    """The oracle (plain single-threaded C loops, one per worker) timed on the host:
+    all cores on every rows_step-th row of the headline view (the reported value);
+    one core on a band of that view's rows and on the whole 640 x 480 view; all cores
+    on row samples of the uneven 64-view batch and of the stress batch's 512 x 512
+    views.  Samples are spread over each image so their cost mix is the image's."""
+    import numpy as np
+
+    import oracle
     from paper_2007_00745_amd import workloads
+
+    def band(v, step, offset=0):
+        return [(v, [int(r)]) for r in range(offset, v.m, step)]
+
+    total, dt = _oracle_rows(band(view, rows_step), threads)
+    nrows = len(range(0, view.m, rows_step))
+    # one core: every 32nd row of the headline view (about 10 s on one core)
+    s_band, d_band = _oracle_rows(band(view, 32, 16), 1)
+    # one core on the small 640 x 480 view, whole image
     c1 = workloads.c1()
     t1 = time.perf_counter()
     img = oracle.render(c1.window, c1.m, c1.n, c1.max_iter, c1.R)
     d1 = time.perf_counter() - t1
     s1 = int(img.sum(dtype=np.int64))
+    # all cores: every 32nd row of every view of the uneven batch, every 128th row of
+    # every small view of the stress batch (rows offset so that both halves are hit)
+    c3 = workloads.c3()
+    s3, d3 = _oracle_rows([t for v in c3 for t in band(v, 32, 7)], threads)
+    c5s = workloads.c5()[1:]
+    s5, d5 = _oracle_rows([t for v in c5s for t in band(v, 128, 61)], threads)
     import platform
     import subprocess
     try:
@@ -139,13 +177,28 @@ def cpu_baseline(view, rows_step: int, threads: int) -> dict:
             "usable_cpus": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity")
             else None,
             "compiler": gcc, "cflags": " ".join(oracle.CFLAGS)}
-    return {"value": total / dt, "unit": "pixel-iterations/s", "cores": threads,
+    unit = "pixel-iterations/s"
+    return {"value": total / dt, "unit": unit, "cores": threads,
             "kind": "oracle", "host": host,
             "sample": f"rows i = 0 mod {rows_step} of the {view.m}x{view.n} view "
-                      f"({len(rows)} rows, {idx.size} px, {total} iterations, {dt:.2f} s wall)",
-            "single_core": {"value": s1 / d1, "seconds": d1, "iterations": s1,
-                            "workload": f"{c1.m}x{c1.n} full view, max_iter {c1.max_iter}, "
-                                        "whole image, one thread"}}
+                      f"({nrows} rows, {nrows * view.n} px, {total} iterations, {dt:.2f} s "
+                      f"wall), one row per task, {threads} worker threads",
+            "single_core": {"value": s_band / d_band, "unit": unit, "seconds": d_band,
+                            "iterations": s_band,
+                            "workload": f"rows i = 16 mod 32 of the {view.m}x{view.n} view, "
+                                        "one thread"},
+            "single_core_small_view": {"value": s1 / d1, "unit": unit, "seconds": d1,
+                                       "iterations": s1,
+                                       "workload": f"{c1.m}x{c1.n} full view, max_iter "
+                                                   f"{c1.max_iter}, whole image, one thread"},
+            "all_core_uneven_batch": {"value": s3 / d3, "unit": unit, "cores": threads,
+                                      "seconds": d3, "iterations": s3,
+                                      "workload": "rows i = 7 mod 32 of every view of the "
+                                                  "uneven 64-view batch"},
+            "all_core_stress_small_views": {"value": s5 / d5, "unit": unit, "cores": threads,
+                                            "seconds": d5, "iterations": s5,
+                                            "workload": "rows i = 61 mod 128 of each of the "
+                                                        "stress batch's 4096 views of 512^2"}}
 
 
 # Computation times of the paper's alternating-row run with 32 MPI tasks on two Xeon
@@ -356,34 +409,50 @@ def tail_fraction(st, clock_khz):
             "tail_fraction": (st[6] - st[5]) / (st[6] - st[4])}
 
 
-def train_cost_model(torch, native, workloads, costmodel):
+# Tiling of the batch plans whose queue orders are compared: the learned step probes
+# every tile (64 probes of up to 128 updates), so coarse tiles keep that cost small,
+# and 4 row parts per tile keep the queue's grain fine.  On the uneven batch the
+# learned order with 64 x 8 tiles gained 1.4 of the 4.2 ms between FCFS and the
+# true-cost order, with 128 x 16 tiles 3.5 of 4.7 ms (probe features 1.44 vs 0.38 ms).
+BATCH_TUNING = {"tile_w": 128, "tile_h": 16, "tile_parts": 4}
+
+
+def train_cost_model(torch, native, workloads, costmodel, tuning=None, per_seed: int = 4):
     """Cost model for the ordered launches: tile costs logged from views of the
-    uneven-batch distribution (seeds 1000-1015) and four full views of other
-    sizes and limits, 200k tiles sampled, 30 epochs of Adam (all in the kernels)."""
+    uneven-batch distribution (seeds 1000-1015, per_seed views each) and four full
+    views of other sizes and limits, on tiles of the given tuning; 200k tiles
+    sampled, 30 epochs of Adam (all in the kernels)."""
     t0 = time.perf_counter()
-    tv = workloads.training_views(range(1000, 1016), per_seed=4)
+    tv = workloads.training_views(range(1000, 1016), per_seed=per_seed)
     tv += [workloads.c2(side, mi) for side, mi in ((1024, 2000), (2048, 5000), (1536, 20000),
                                                    (768, 800))]
-    feat, target, _, tplan = costmodel.collect(tv)
+    feat, target, _, tplan = costmodel.collect(tv, tuning=tuning)
     params, losses = costmodel.train(feat, target, epochs=30, batch=512, lr=1e-3, seed=0)
     torch.cuda.synchronize()
-    info = {"train_tiles_logged": int(tplan.ntiles),
+    info = {"train_views": len(tv), "train_tiles_logged": int(tplan.ntiles),
             "train_samples": min(int(tplan.ntiles), 200000), "epochs": 30, "batch": 512,
-            "final_train_loss": losses[-1], "seconds": time.perf_counter() - t0}
+            "tiling": tplan.tuning, "final_train_loss": losses[-1],
+            "seconds": time.perf_counter() - t0}
     tplan.close()
     return params, info
 
 
 def makespans(torch, native, workloads, costmodel, reps: int, clock_khz: float,
-              params, cus: int) -> dict:
-    """Uneven 64-view batch: per-view row partitions and FCFS vs one batched launch."""
+              cus: int) -> dict:
+    """Uneven 64-view batch: per-view row partitions and FCFS vs one batched launch.
+    The queue orders are compared on one plan of BATCH_TUNING tiles, with a cost model
+    trained on tiles of that shape; the autotuner's own pick is timed in FCFS order
+    beside them."""
     res = {}
     views = workloads.c3()
     log(f"makespan: {len(views)} views, {sum(v.pixels for v in views)} px")
+    params, res["cost_model_training"] = train_cost_model(torch, native, workloads, costmodel,
+                                                          tuning=BATCH_TUNING, per_seed=8)
     t0 = time.perf_counter()
     tun, trials = native.autotune(views)
     res["autotune"] = {"tuning": tun, "trials": trials, "seconds": time.perf_counter() - t0}
-    plan = native.Plan(views, tun)
+    plan = native.Plan(views, BATCH_TUNING)
+    res["tuning"] = plan.tuning
     out = torch.empty(plan.out_size(), dtype=torch.int32, device="cuda")
     cost = torch.empty(plan.ntiles, dtype=torch.int64, device="cuda")
     stats = torch.zeros(8, dtype=torch.int64, device="cuda")
@@ -442,6 +511,15 @@ def makespans(torch, native, workloads, costmodel, reps: int, clock_khz: float,
 
     res["cost_model_eval"] = costmodel.evaluate(params, plan.features(),
                                                 native.cost_targets(cost))
+    # the autotuner's pick, FCFS order
+    aplan = native.Plan(views, tun)
+    aout = torch.empty(aplan.out_size(), dtype=torch.int32, device="cuda")
+    ms["batched_fcfs_autotuned"] = dict(
+        timed_stats(torch, lambda: aplan.launch(aout, use_graph=True), reps,
+                    "batched fcfs, autotuned plan"), tiling=aplan.tuning)
+    assert torch.equal(aout, ref), "the autotuned plan changed the counts"
+    aplan.close()
+    del aout
     true_perm = torch.argsort(cost, descending=True).to(torch.int32)
     names = {"fcfs": "fcfs", "probe": "probe_lpt", "learned": "learned_lpt",
              "ordered": "true_cost_lpt"}
@@ -457,6 +535,12 @@ def makespans(torch, native, workloads, costmodel, reps: int, clock_khz: float,
         st = [int(v) for v in stats.cpu().tolist()]
         ms[f"batched_{names[mode]}"] = dict(rec, tail=tail_fraction(st, clock_khz))
     res["makespan_ms"] = ms
+    f, lrn, tru = (ms[k]["median_ms"] for k in ("batched_fcfs", "batched_learned_lpt",
+                                                "batched_true_cost_lpt"))
+    # what the trained network gains over its FCFS fallback on the same plan, as a share
+    # of what the true-cost order (known only after a render) gains
+    res["learned_gain_share_of_true_cost_gain_medians"] = ((f - lrn) / (f - tru) if f > tru
+                                                           else None)
     static = min(ms["static_rows_per_view"]["ms"], ms["alternating_rows_per_view"]["ms"])
     res["speedup_batched_learned_vs_static_rows"] = static / ms["batched_learned_lpt"]["ms"]
     res["speedup_batched_fcfs_vs_static_rows"] = static / ms["batched_fcfs"]["ms"]
@@ -473,6 +557,58 @@ def makespans(torch, native, workloads, costmodel, reps: int, clock_khz: float,
         "batched_fcfs_vs_static_rows": static_med / ms["batched_fcfs"]["median_ms"],
         "batched_learned_vs_concatenated_rows": concat_med / ms["batched_learned_lpt"]["median_ms"],
         "batched_fcfs_vs_concatenated_rows": concat_med / ms["batched_fcfs"]["median_ms"]}
+    plan.close()
+    return res
+
+
+def profile_batch(torch, native, workloads, costmodel, steps: int) -> dict:
+    """Counter runs on the uneven batch (plan of BATCH_TUNING tiles): the features,
+    inference and ordered-render kernels, each launched `steps` times between events;
+    returns the figures that turn per-dispatch counters into per-iteration rates."""
+    views = workloads.c3()
+    torch.cuda.set_device(0)
+    plan = native.Plan(views, BATCH_TUNING)
+    out = torch.empty(plan.out_size(), dtype=torch.int32, device="cuda")
+    cost = torch.empty(plan.ntiles, dtype=torch.int64, device="cuda")
+    stats = torch.zeros(8, dtype=torch.int64, device="cuda")
+    plan.launch(out, tile_cost=cost)
+    torch.cuda.synchronize()
+    sum_counts = int(cost.sum().item())
+    feat = torch.empty((plan.ntiles, native.NFEAT), dtype=torch.float32, device="cuda")
+    params = costmodel.init_params(0)
+    keys = torch.empty(plan.ntiles, dtype=torch.float32, device="cuda")
+
+    def timed(fn):
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(steps)]
+        for a, b in ev:
+            a.record()
+            fn()
+            b.record()
+        torch.cuda.synchronize()
+        return [a.elapsed_time(b) for a, b in ev]
+
+    res = {"workload": "uneven 64-view batch (seed 745)", "tuning": plan.tuning,
+           "tiles": plan.ntiles, "sum_counts": sum_counts}
+    res["features_ms"] = timed(lambda: plan.features(feat))
+    f = feat.cpu().numpy()[:, 4:].astype("float64")
+    import numpy as np
+    caps = np.minimum(np.array([v.max_iter for v in views]), 128)
+    # probe iterations = sum of min(count, cap) over all probes, from the features
+    tile_view = np.repeat(np.arange(len(views)),
+                          [native.tile_count(v.m, v.n, plan.tuning["tile_w"],
+                                             plan.tuning["tile_h"]) for v in views])
+    cap_t = caps[tile_view][:, None].astype(np.float64)
+    res["probe_iterations"] = int(np.rint(np.exp(f * np.log1p(cap_t)) - 1).sum())
+    res["mlp_ms"] = timed(lambda: native.mlp_forward(params, feat, keys))
+    true_perm = native.order_desc(native.cost_targets(cost))
+    res["render_ms"] = timed(lambda: plan.launch(out, mode="ordered", order=true_perm,
+                                                 stats=stats))
+    torch.cuda.synchronize()
+    st = [int(v) for v in stats.cpu().tolist()]
+    res["render_wave_iterations_per_launch"] = st[0] / steps
+    res["lane_occupancy"] = st[1] / (64.0 * st[0]) if st[0] else None
+    assert int(out.sum(dtype=torch.int64).item()) == sum_counts
     plan.close()
     return res
 
@@ -663,6 +799,12 @@ def main():
                          "then the ordered render (true-cost order) is launched only as it "
                          "is timed, --steps times; no training, no steps of the whole path, "
                          "no comparisons, makespans or CPU baseline")
+    ap.add_argument("--profile-batch", action="store_true",
+                    help="run for counters on the uneven 64-view batch: one FCFS launch logs "
+                         "the tile costs, then --steps launches each of the probe-feature "
+                         "kernel, the cost-model inference kernel (untrained weights) and the "
+                         "ordered render in the true-cost order, on the plan the makespan "
+                         "comparison uses; prints one JSON line and nothing else runs")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -674,6 +816,10 @@ def main():
     from paper_2007_00745_amd import costmodel, native, workloads
 
     native.lib()  # fails loudly when the library is missing
+    if args.profile_batch:
+        print(json.dumps(profile_batch(torch, native, workloads, costmodel, args.steps)),
+              flush=True)
+        return
     view = workloads.c2(args.side, args.max_iter)
     torch.cuda.set_device(0)
     dinfo = native.device_info()
@@ -884,7 +1030,7 @@ def main():
         res["deep_zoom_double_double"] = deep_zoom(torch, native)
     if not args.no_makespan:
         res["makespan"] = makespans(torch, native, workloads, costmodel, args.makespan_reps,
-                                    clock_khz, params, int(dinfo["compute_units"]))
+                                    clock_khz, int(dinfo["compute_units"]))
     if not args.no_stress:
         res["stress_batch"] = stress_batch(torch, native, workloads, costmodel, 1, clock_khz,
                                            params, int(dinfo["compute_units"]),

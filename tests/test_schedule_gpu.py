@@ -108,6 +108,18 @@ def test_learned_order_vs_fcfs():
     assert ev["spearman"] > 0.6
 
     true_perm = torch.argsort(cost, descending=True).to(torch.int32)
+    # What the network gains without timing noise: the logged tile costs list-scheduled
+    # on the device's resident wavefronts (Graham) in each queue order.  FCFS takes the
+    # views in submission order, so an expensive view submitted late finishes last.
+    c = cost.cpu().numpy()
+    W = int(native.device_info()["compute_units"]) * 28
+    keys = native.mlp_forward(params, plan.features())
+    learned = native.order_desc(keys).cpu().numpy()
+    lsm = {name: _list_schedule(c, order, W) for name, order in
+           (("fcfs", np.arange(plan.ntiles)), ("learned", learned),
+            ("true_cost", np.argsort(-c, kind="stable")))}
+    _log(f"list-schedule makespans (iterations per wave, W={W}): {lsm}")
+    assert lsm["true_cost"] <= lsm["learned"] < lsm["fcfs"]
     ms = {}
     for mode, kw in (("fcfs", {}), ("probe", {}), ("learned", dict(mlp=params)),
                      ("ordered", dict(order=true_perm))):
@@ -115,7 +127,9 @@ def test_learned_order_vs_fcfs():
         ms[mode] = _timed(lambda: plan.launch(out, mode=mode, use_graph=True, **kw))
         assert torch.equal(out, ref), mode
     _log(f"makespan ms: {ms}; learned gain over FCFS {100 * (1 - ms['learned'] / ms['fcfs']):.1f}%")
-    assert ms["learned"] < 1.5 * ms["fcfs"]
+    # sanity bound only (timings of this small batch vary by a few per cent from box to
+    # box): probing, inference and ordering must not cost a large share of the launch
+    assert ms["learned"] < 1.10 * ms["fcfs"]
     _sample_check(plan, out, np.random.default_rng(3), per_view=64)
     plan.close()
     tplan.close()
@@ -135,7 +149,7 @@ def test_stress_batch_c5():
     assert st[3] == plan.ntiles
     rng = np.random.default_rng(747)
     deep = views[0]
-    idx = rng.integers(0, deep.pixels, 2048)
+    idx = rng.integers(0, deep.pixels, 16384)
     got = out[torch.tensor(idx, device="cuda")].cpu().numpy()
     want = oracle.render_pixels(deep.window, deep.m, deep.n, deep.max_iter, deep.R, idx,
                                 threads=16)
@@ -203,20 +217,27 @@ def test_bench_configuration_8192(quick_model):
         p.close()
 
 
-def test_bench_configuration_batch(quick_model):
-    # The batched learned launch of the benchmark's makespan comparison, at full size
-    # (the 64-view batch, autotuned plan); sampled pixels of every view.
+@pytest.mark.parametrize("which", ["bench_tiling", "autotuned"])
+def test_bench_configuration_batch(quick_model, which):
+    # The batched launches of the benchmark's makespan comparison, at full size (the
+    # 64-view batch): the learned order on the benchmark's coarse-tile plan, and FCFS
+    # on the autotuner's pick; sampled pixels of every view, then every pixel against
+    # the oracle's whole-image digests.
+    import bench
     views = workloads.c3()
-    tun, _ = native.autotune(views)
+    if which == "autotuned":
+        tun, _ = native.autotune(views)
+        kw = {}
+    else:
+        tun, kw = bench.BATCH_TUNING, dict(mode="learned", mlp=quick_model)
     plan = native.Plan(views, tun)
     out = torch.full((plan.out_size(),), -1, dtype=torch.int32, device="cuda")
-    plan.launch(out, mode="learned", mlp=quick_model, use_graph=True)
+    plan.launch(out, use_graph=True, **kw)
     torch.cuda.synchronize()
     assert int(out.min().item()) >= 1
     _sample_check(plan, out, np.random.default_rng(745), per_view=48)
     gold = _golden("c3")
     if gold is not None:
-        # every pixel of every view against the oracle's whole images
         imgs = plan.view_images(out.cpu())
         assert len(gold) == len(imgs)
         for k, (img, g) in enumerate(zip(imgs, gold)):
