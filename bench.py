@@ -414,7 +414,9 @@ def tail_fraction(st, clock_khz):
 # and 4 row parts per tile keep the queue's grain fine.  On the uneven batch the
 # learned order with 64 x 8 tiles gained 1.4 of the 4.2 ms between FCFS and the
 # true-cost order, with 128 x 16 tiles 3.5 of 4.7 ms (probe features 1.44 vs 0.38 ms).
-BATCH_TUNING = {"tile_w": 128, "tile_h": 16, "tile_parts": 4}
+# Deferred blocks of at most 128 updates: escapes are dense in these boundary zooms,
+# and the batch took 305 ms in FCFS order against 316 ms with blocks of 1024.
+BATCH_TUNING = {"tile_w": 128, "tile_h": 16, "tile_parts": 4, "block_iters": 128}
 
 
 def train_cost_model(torch, native, workloads, costmodel, tuning=None, per_seed: int = 4):

@@ -447,7 +447,8 @@ int mandel_cost_targets(const int64_t *cost, int64_t n, float *target, void *str
 
 /*
  * mandel_plan_autotune -- picks the plan tuning (tile shape, claim grain,
- * waves per workgroup) for a batch by timing every candidate on a sample of
+ * waves per workgroup, row parts, longest deferred block) for a batch by
+ * timing every candidate on a sample of
  * the views (at most max_sample views, spread over the batch's range of
  * pixels x max_iter), and caches the choice per device and batch signature.
  * Synchronous: it allocates a scratch image, renders the sample several
