@@ -136,8 +136,9 @@ def test_learned_order_vs_fcfs():
 
 
 def test_stress_batch_c5():
+    # in the benchmark's configuration (64x8 tiles, blocks of at most 128 updates)
     views = workloads.c5()
-    plan = native.Plan(views)
+    plan = native.Plan(views, {"block_iters": 128})
     _log(f"c5: {plan.ntiles} tiles, {plan.npixels} px")
     out = torch.full((plan.out_size(),), -1, dtype=torch.int32, device="cuda")
     stats = torch.zeros(8, dtype=torch.int64, device="cuda")
