@@ -143,8 +143,8 @@ def cpu_baseline(view, rows_step: int, threads: int) -> dict:
 
     total, dt = _oracle_rows(band(view, rows_step), threads)
     nrows = len(range(0, view.m, rows_step))
-    # one core: every 32nd row of the headline view (about 10 s on one core)
-    s_band, d_band = _oracle_rows(band(view, 32, 16), 1)
+    # one core: every 24th row of the headline view (about 12 s on one core)
+    s_band, d_band = _oracle_rows(band(view, 24, 12), 1)
     # one core on the small 640 x 480 view, whole image
     c1 = workloads.c1()
     t1 = time.perf_counter()
@@ -185,7 +185,7 @@ def cpu_baseline(view, rows_step: int, threads: int) -> dict:
                       f"wall), one row per task, {threads} worker threads",
             "single_core": {"value": s_band / d_band, "unit": unit, "seconds": d_band,
                             "iterations": s_band,
-                            "workload": f"rows i = 16 mod 32 of the {view.m}x{view.n} view, "
+                            "workload": f"rows i = 12 mod 24 of the {view.m}x{view.n} view, "
                                         "one thread"},
             "single_core_small_view": {"value": s1 / d1, "unit": unit, "seconds": d1,
                                        "iterations": s1,
