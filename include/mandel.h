@@ -327,8 +327,9 @@ typedef struct mandel_launch {
     int64_t *tile_cost;      /* device int64[ntiles] or NULL: sum of counts per tile */
     uint64_t *stats;         /* device uint64[8] or NULL (as in mandel_sched) */
     int32_t probe_cap;       /* PROBE_LPT / LEARNED_LPT: probe iteration cap of the
-                                features (see mandel_plan_features) [128]; a model
-                                must be used with the cap it was trained with */
+                                features, absolute (> 0) or a share of each view's
+                                max_iter (< 0; see mandel_plan_features) [128]; a
+                                model must be used with the cap it was trained with */
     int32_t workers;         /* STATIC_ROWS / ALTERNATING_ROWS: W workgroups of the
                                 plan's waves_per_group wavefronts (required >= 1);
                                 must be 0 in the other modes */
@@ -396,8 +397,12 @@ int mandel_plan_destroy(mandel_plan *plan);
  *             probe pixel at column x0 + floor((k + 0.5) w / 8) and row
  *             y0 + floor((r + 0.5) h / 8) of the (clipped) w x h tile, where
  *             count is that pixel's escape-time count (same definition and
- *             arithmetic as the render) and cap = min(max_iter, probe_cap).
- *   probe_cap  1 .. 2^20, or 0 for 128.
+ *             arithmetic as the render) and cap is the view's probe cap:
+ *             min(max_iter, probe_cap) for probe_cap > 0, and
+ *             max(1, floor(max_iter / k)) for probe_cap = -k (a share of the
+ *             view's own limit, so the probes of deep, high-limit views still
+ *             tell late escapes from points that never escape).
+ *   probe_cap  -2^20 .. 2^20; 0 means 128.
  */
 int mandel_plan_features(mandel_plan *plan, float *feat, int32_t probe_cap, void *stream);
 

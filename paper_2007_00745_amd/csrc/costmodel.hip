@@ -47,6 +47,16 @@ __device__ __forceinline__ int32_t find_view_b(ConstViewDesc *views, int32_t nvi
     return lo;
 }
 
+// Probe cap of a view: min(max_iter, probe_cap) for probe_cap > 0; for probe_cap = -k
+// (k >= 1) a share of the view's own limit, max(1, floor(max_iter / k)).
+__device__ __forceinline__ int32_t probe_cap_of(int32_t max_iter, int32_t probe_cap)
+{
+    if (probe_cap > 0)
+        return max_iter < probe_cap ? max_iter : probe_cap;
+    const int32_t c = max_iter / -probe_cap;
+    return c > 1 ? c : 1;
+}
+
 // ---- probe features: one wavefront per tile, one probe pixel per lane ------
 constexpr int32_t PROBE_BLOCK = 8;   // updates per untested block
 constexpr int32_t PROBE_REPLAYS = 2; // replays before a wave tests every update
@@ -81,7 +91,7 @@ __global__ void __launch_bounds__(256) features_kernel(const ViewDesc *views, in
     const double py = offy * vd.dy;
     const double cx = vd.cx0 + px;
     const double cy = vd.cy0 + py;
-    const int32_t cap = vd.max_iter < probe_cap ? vd.max_iter : probe_cap;
+    const int32_t cap = probe_cap_of(vd.max_iter, probe_cap);
     // min(count, cap) needs the tests of z_1 .. z_{cap-1} only: count >= cap gives cap.
     // The wave advances in blocks of up to PROBE_BLOCK updates.  While no lane has
     // escaped and every lane's |c| lies in the disk where an escaped orbit keeps
@@ -147,13 +157,13 @@ __global__ void __launch_bounds__(256) features_kernel(const ViewDesc *views, in
 }
 
 // ---- probe-sum heuristic key: ln(1 + sum of the (capped) probe counts) ------
-__global__ void probe_key_kernel(const float *feat, int64_t n, float probe_cap, float *keys)
+__global__ void probe_key_kernel(const float *feat, int64_t n, int32_t probe_cap, float *keys)
 {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n)
         return;
     const float *f = feat + t * NF;
-    const float cap = fminf(rintf(expf(f[3])), probe_cap);
+    const float cap = (float)probe_cap_of((int32_t)rintf(expf(f[3])), probe_cap);
     const float L = logf(1.0f + cap);
     float s = 0.0f;
     for (int k = 0; k < 64; ++k)
@@ -612,7 +622,7 @@ hipError_t launch_probe_key(const float *feat, int64_t n, int32_t probe_cap, flo
                             hipStream_t s)
 {
     hipLaunchKernelGGL(probe_key_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, feat, n,
-                       (float)probe_cap, keys);
+                       probe_cap, keys);
     return hipGetLastError();
 }
 

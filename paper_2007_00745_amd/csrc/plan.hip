@@ -372,8 +372,8 @@ int mandel_plan_launch(mandel_plan *p, int32_t *out, const mandel_launch *args, 
         return fail(MANDEL_EINVAL, "row stealing applies to the queue modes only");
     if (la.probe_cap == 0)
         la.probe_cap = 128;
-    if (la.probe_cap < 1 || la.probe_cap > (1 << 20))
-        return fail(MANDEL_EINVAL, "probe_cap=%d outside [1, 2^20]", la.probe_cap);
+    if (la.probe_cap < -(1 << 20) || la.probe_cap > (1 << 20))
+        return fail(MANDEL_EINVAL, "probe_cap=%d outside [-2^20, 2^20]", la.probe_cap);
     if (la.first_slot < 0)
         return fail(MANDEL_EINVAL, "negative first_slot");
     if (la.periodicity != 0 && la.periodicity != 1)
@@ -463,8 +463,8 @@ int mandel_plan_features(mandel_plan *p, float *feat, int32_t probe_cap, void *s
         return fail(MANDEL_EINVAL, "plan is NULL");
     if (probe_cap == 0)
         probe_cap = 128;
-    if (probe_cap < 1 || probe_cap > (1 << 20))
-        return fail(MANDEL_EINVAL, "probe_cap=%d outside [1, 2^20]", probe_cap);
+    if (probe_cap < -(1 << 20) || probe_cap > (1 << 20))
+        return fail(MANDEL_EINVAL, "probe_cap=%d outside [-2^20, 2^20]", probe_cap);
     if (p->ntiles == 0)
         return MANDEL_OK;
     if (!feat)

@@ -822,8 +822,13 @@ render_kernel(RenderArgs a)
                 // bound of every remaining lane's distance to its deadline.
                 if (budget >= 4) {
                     cmask = ballot(active);
+                    // with deferred tests, only while some lane still needs a test after
+                    // every update (a replay, an unsafe or a young lane); otherwise the
+                    // round ends and the wave returns to untested blocks
                     if (cmask != 0 && ((uint32_t)__popcll(~cmask) < R || exhausted) &&
-                        (!DEFER || done + 4 < climit)) {
+                        (!DEFER ||
+                         (done + 4 < climit &&
+                          ballot(active && (pending || !safe || (W - start) < P)) != 0))) {
                         budget -= 4;
                         done += 4;
                         continue;

@@ -281,14 +281,16 @@ def test_features_probe_counts(small_batch):
     views, _ = small_batch
     tw, th = 64, 8
     plan = native.Plan(views, dict(tile_w=tw, tile_h=th))
-    for cap_arg in (0, 7, 300):
+    # caps: the default (128), absolute ones, and shares of each view's max_iter
+    # (probe_cap = -k: cap = max(1, max_iter // k)), down to a cap of 1
+    for cap_arg in (0, 7, 300, -1, -16, -(1 << 20)):
         feat = plan.features(probe_cap=cap_arg).cpu().double().numpy()
         cap_req = 128 if cap_arg == 0 else cap_arg
         t = 0
         for v in views:
             if v.m == 0 or v.n == 0:
                 continue
-            cap = min(v.max_iter, cap_req)
+            cap = min(v.max_iter, cap_req) if cap_req > 0 else max(1, v.max_iter // -cap_req)
             ty, tx = -(-v.m // th), -(-v.n // tw)
             for a in range(ty):
                 for b in range(tx):
