@@ -58,7 +58,7 @@ __device__ __forceinline__ int32_t probe_cap_of(int32_t max_iter, int32_t probe_
 }
 
 // ---- probe features: one wavefront per tile, one probe pixel per lane ------
-constexpr int32_t PROBE_BLOCK = 8;   // updates per untested block
+constexpr int32_t PROBE_BLOCK = 16;  // updates per untested block
 constexpr int32_t PROBE_REPLAYS = 2; // replays before a wave tests every update
 
 __global__ void __launch_bounds__(256) features_kernel(const ViewDesc *views, int32_t nviews,
@@ -117,8 +117,14 @@ __global__ void __launch_bounds__(256) features_kernel(const ViewDesc *views, in
         const int32_t L = cap - 1 - it < PROBE_BLOCK ? cap - 1 - it : PROBE_BLOCK;
         if (replays < PROBE_REPLAYS) {
             const double xs = x, ys = y;
-            for (int32_t u = 0; u < L; ++u)
-                update();
+            if (L == PROBE_BLOCK) {
+#pragma unroll
+                for (int32_t u = 0; u < PROBE_BLOCK; ++u)
+                    update();
+            } else {
+                for (int32_t u = 0; u < L; ++u)
+                    update();
+            }
             const bool esc = live && !(x * x + y * y <= R2);
             if (__builtin_amdgcn_ballot_w64(esc) == 0) {
                 it += L;
