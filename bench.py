@@ -673,6 +673,24 @@ def stress_batch(torch, native, workloads, costmodel, reps: int, clock_khz: floa
         st = [int(v) for v in stats.cpu().tolist()]
         ms[name] = {"ms": t, "pixel_iterations_per_s": sum_counts / (t / 1e3),
                     "tail": tail_fraction(st, clock_khz)}
+    # The same batch with collapsed rows: the deep view's row pitch lies below the
+    # spacing of doubles near its centre, so neighbouring rows share their imaginary part
+    # (and counts); each distinct row is rendered once and copied out after the render.
+    cplan = native.Plan(views, {"block_iters": 128, "collapse_rows": 1})
+    ccost = torch.empty(cplan.ntiles, dtype=torch.int64, device="cuda")
+    out.fill_(-1)
+    cplan.launch(out, tile_cost=ccost)
+    torch.cuda.synchronize()
+    assert torch.equal(out, ref), "collapsed rows changed the counts"
+    rendered = int(ccost.sum().item())
+    out.fill_(-1)
+    t = timed_ms(torch, lambda: cplan.launch(out, use_graph=True), reps, "stress fcfs collapsed")
+    assert torch.equal(out, ref), "collapsed rows changed the counts"
+    ms["fcfs_collapsed_rows"] = {"ms": t, "tiles": cplan.ntiles,
+                                 "iterations_executed": rendered,
+                                 "pixel_iterations_per_s_of_the_image": sum_counts / (t / 1e3),
+                                 "executed_iterations_per_s": rendered / (t / 1e3)}
+    cplan.close()
     res["makespan_ms"] = ms
     res["row_workers"] = W
     best_rows = min(ms[k]["ms"] for k in ("static_rows_concatenated",

@@ -276,7 +276,18 @@ typedef struct mandel_tuning {
     int32_t groups;          /* persistent workgroups [fill the device] */
     int32_t refill_lanes;    /* [16], as in mandel_sched */
     int32_t tile_parts;      /* [1], as in mandel_sched */
-    int32_t reserved;
+    int32_t collapse_rows;   /* 1: render each distinct row coordinate once.  Where a
+                                view's pitch dy lies below the spacing of doubles near
+                                its centre, neighbouring rows get the same imaginary part
+                                (cy0 + ((i + 0.5) - m/2) dy rounds to equal values) and so
+                                the same counts.  Such a view is rendered as one row per
+                                distinct value into the first rows of its image, and the
+                                rows are then copied to their places (extra kernels after
+                                the render, in the same launch).  The image is identical;
+                                tile ids, tile costs, features, statistics and the row
+                                partitions (STATIC_ROWS / ALTERNATING_ROWS) then refer to
+                                the collapsed rows, and first_slot must be 0.  Views
+                                whose rows are all distinct are unchanged.  0: off [0] */
 } mandel_tuning;
 
 typedef struct mandel_plan mandel_plan;

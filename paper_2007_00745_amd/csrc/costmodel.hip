@@ -62,9 +62,9 @@ constexpr int32_t PROBE_BLOCK = 16;  // updates per untested block
 constexpr int32_t PROBE_REPLAYS = 2; // replays before a wave tests every update
 
 __global__ void __launch_bounds__(256) features_kernel(const ViewDesc *views, int32_t nviews,
-                                                       int64_t ntiles, int32_t tile_w,
-                                                       int32_t tile_h, int32_t probe_cap,
-                                                       float *feat)
+                                                       const double *ytab, int64_t ntiles,
+                                                       int32_t tile_w, int32_t tile_h,
+                                                       int32_t probe_cap, float *feat)
 {
     // one tile per wavefront: t is the same in all 64 lanes
     const int64_t t = (int64_t)blockIdx.x * (blockDim.x / 64) +
@@ -86,11 +86,16 @@ __global__ void __launch_bounds__(256) features_kernel(const ViewDesc *views, in
     const int32_t j = x0 + (int32_t)(((int64_t)(2 * k + 1) * w) / 16);
     const int32_t i = y0 + (int32_t)(((int64_t)(2 * r + 1) * h) / 16);
     const double offx = ((double)j + 0.5) - 0.5 * (double)vd.n;
-    const double offy = ((double)i + 0.5) - 0.5 * (double)vd.m;
     const double px = offx * vd.dx;
-    const double py = offy * vd.dy;
     const double cx = vd.cx0 + px;
-    const double cy = vd.cy0 + py;
+    double cy;
+    if (vd.ytab_off >= 0) { // collapsed rows: the row's coordinate from the plan's table
+        cy = ytab[vd.ytab_off + i];
+    } else {
+        const double offy = ((double)i + 0.5) - 0.5 * (double)vd.m;
+        const double py = offy * vd.dy;
+        cy = vd.cy0 + py;
+    }
     const int32_t cap = probe_cap_of(vd.max_iter, probe_cap);
     // min(count, cap) needs the tests of z_1 .. z_{cap-1} only: count >= cap gives cap.
     // The wave advances in blocks of up to PROBE_BLOCK updates.  While no lane has
@@ -152,8 +157,10 @@ __global__ void __launch_bounds__(256) features_kernel(const ViewDesc *views, in
             val = (float)(vd.cx0 +
                           (((double)x0 + 0.5 * (double)w) - 0.5 * (double)vd.n) * vd.dx);
         else if (lane == 1)
-            val = (float)(vd.cy0 +
-                          (((double)y0 + 0.5 * (double)h) - 0.5 * (double)vd.m) * vd.dy);
+            val = (float)(vd.ytab_off >= 0
+                              ? ytab[vd.ytab_off + y0 + h / 2]
+                              : vd.cy0 + (((double)y0 + 0.5 * (double)h) - 0.5 * (double)vd.m) *
+                                             vd.dy);
         else if (lane == 2)
             val = log10f((float)((double)w * vd.dx));
         else
@@ -616,11 +623,12 @@ unsigned blocks_for(int64_t n, int threads, int64_t cap = 1 << 30)
 
 } // namespace
 
-hipError_t launch_features(const ViewDesc *views, int32_t nviews, int64_t ntiles, int32_t tile_w,
-                           int32_t tile_h, int32_t probe_cap, float *feat, hipStream_t s)
+hipError_t launch_features(const ViewDesc *views, int32_t nviews, const double *ytab,
+                           int64_t ntiles, int32_t tile_w, int32_t tile_h, int32_t probe_cap,
+                           float *feat, hipStream_t s)
 {
     hipLaunchKernelGGL(features_kernel, dim3(blocks_for(ntiles, 4)), dim3(256), 0, s, views,
-                       nviews, ntiles, tile_w, tile_h, probe_cap, feat);
+                       nviews, ytab, ntiles, tile_w, tile_h, probe_cap, feat);
     return hipGetLastError();
 }
 

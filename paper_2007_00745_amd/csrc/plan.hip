@@ -54,6 +54,17 @@ struct mandel_plan {
     int32_t *d_chunk = nullptr;
     int32_t *d_active = nullptr;
     int64_t active_len = 0;
+    // collapsed rows (tuning.collapse_rows): the distinct row coordinates of every
+    // collapsed view, each full row's compressed row, and the in-place copy passes
+    // that expand a collapsed view's image after the render
+    double *d_ytab = nullptr;
+    int32_t *d_rmap = nullptr;
+    struct Expand {
+        int32_t view;
+        int64_t rmap_off;
+        int32_t lo, hi;
+    };
+    std::vector<Expand> expands;
     hipStream_t capture = nullptr;
     std::vector<GraphEntry> graphs;
 };
@@ -92,6 +103,8 @@ int fill_tuning(const mandel_tuning *t, mandel_tuning *o)
     d.refill_lanes = c.refill_lanes;
     d.tile_parts = c.tile_parts;
     d.groups = c.workers;
+    if (d.collapse_rows != 0 && d.collapse_rows != 1)
+        return fail(MANDEL_EINVAL, "collapse_rows must be 0 or 1");
     *o = d;
     return MANDEL_OK;
 }
@@ -202,7 +215,8 @@ int enqueue(mandel_plan *p, int32_t *out, const mandel_launch &la, hipStream_t s
     if (la.mode == MANDEL_PLAN_ORDERED) {
         order = la.order;
     } else if (la.mode == MANDEL_PLAN_PROBE_LPT || la.mode == MANDEL_PLAN_LEARNED_LPT) {
-        e = launch_features(p->d_views, (int32_t)p->views.size(), p->ntiles, p->tune.tile_w,
+        e = launch_features(p->d_views, (int32_t)p->views.size(), p->d_ytab, p->ntiles,
+                            p->tune.tile_w,
                             p->tune.tile_h, la.probe_cap, p->d_feat, s);
         if (e != hipSuccess)
             return hip_fail(e, "features launch");
@@ -234,6 +248,7 @@ int enqueue(mandel_plan *p, int32_t *out, const mandel_launch &la, hipStream_t s
     a.parts = p->tune.tile_parts;
     a.first_slot = la.first_slot;
     a.nrows = p->nrows;
+    a.ytab = p->d_ytab;
     a.out = out;
     a.head = rows ? nullptr : p->d_head;
     a.order = order;
@@ -260,7 +275,53 @@ int enqueue(mandel_plan *p, int32_t *out, const mandel_launch &la, hipStream_t s
     e = launch_render(a, policy, true, test_mode(sc), grid, block, s);
     if (e != hipSuccess)
         return hip_fail(e, "render launch");
+    for (const mandel_plan::Expand &x : p->expands) {
+        const ViewDesc &v = p->views[(size_t)x.view];
+        e = launch_expand_rows(out + v.out_off, v.n, p->d_rmap + x.rmap_off, x.lo, x.hi, s);
+        if (e != hipSuccess)
+            return hip_fail(e, "row expansion launch");
+    }
     return MANDEL_OK;
+}
+
+// Collapsed rows.  Row i of view k has imaginary part cy0 + ((i + 0.5) - m/2) dy (one
+// rounded product, one rounded sum, exactly as the kernels form it); when dy is below
+// the spacing of doubles near cy0, neighbouring rows round to the same value, and rows
+// with equal c have equal counts.  Such a view is rendered as m' <= m rows, one per
+// distinct value (kept in ytab, in row order), into the first m' rows of its image,
+// and afterwards copied out: row i becomes a copy of rendered row rmap[i] <= i.  The
+// copies run in passes over ranges [lo, hi) whose sources all lie below lo, from the
+// bottom of the image up, so no pass reads a row that a pass has already written.
+void collapse_rows(mandel_plan *p, int32_t k, std::vector<double> &ytab,
+                   std::vector<int32_t> &rmap)
+{
+    ViewDesc &d = p->views[(size_t)k];
+    const int32_t m = d.m;
+    std::vector<double> ys;
+    std::vector<int32_t> map((size_t)m);
+    for (int32_t i = 0; i < m; ++i) {
+        const double off = ((double)i + 0.5) - 0.5 * (double)m;
+        const double py = off * d.dy;
+        const double cy = d.cy0 + py;
+        if (ys.empty() || cy != ys.back())
+            ys.push_back(cy);
+        map[(size_t)i] = (int32_t)ys.size() - 1;
+    }
+    if ((int32_t)ys.size() == m)
+        return; // every row distinct
+    d.ytab_off = (int32_t)ytab.size();
+    ytab.insert(ytab.end(), ys.begin(), ys.end());
+    const int64_t rmap_off = (int64_t)rmap.size();
+    rmap.insert(rmap.end(), map.begin(), map.end());
+    d.m = (int32_t)ys.size();
+    d.tiles_y = (int32_t)(((int64_t)d.m + p->tune.tile_h - 1) / p->tune.tile_h);
+    for (int32_t hi = m; hi > 0;) {
+        const int32_t lo = map[(size_t)hi - 1] + 1;
+        if (lo >= hi)
+            break; // rows below hi are all distinct: rendered in place
+        p->expands.push_back({k, rmap_off, lo, hi});
+        hi = lo;
+    }
 }
 
 } // namespace
@@ -286,6 +347,8 @@ int mandel_plan_create(const mandel_view *views, int32_t nviews, const mandel_tu
     p->tune = tu;
     p->views.resize((size_t)nviews);
     int64_t toff = 0, npx = 0;
+    std::vector<double> ytab;
+    std::vector<int32_t> rmap;
     for (int32_t k = 0; k < nviews; ++k) {
         const mandel_view &v = views[k];
         rc = make_view(&v.w, v.m, v.n, v.max_iter, v.R, tu.tile_w, tu.tile_h, &p->views[k]);
@@ -297,11 +360,14 @@ int mandel_plan_create(const mandel_view *views, int32_t nviews, const mandel_tu
             delete p;
             return fail(MANDEL_EINVAL, "view %d: negative out_offset", k);
         }
-        p->views[k].out_off = v.out_offset;
-        p->views[k].tile_off = toff;
-        p->views[k].row_off = p->nrows;
-        toff += tile_count(v.m, v.n, tu.tile_w, tu.tile_h);
-        p->nrows += v.m;
+        ViewDesc &d = p->views[k];
+        d.out_off = v.out_offset;
+        if (tu.collapse_rows && v.m > 1 && v.n > 0)
+            collapse_rows(p, k, ytab, rmap);
+        d.tile_off = toff;
+        d.row_off = p->nrows;
+        toff += tile_count(d.m, d.n, tu.tile_w, tu.tile_h);
+        p->nrows += d.m;
         npx += (int64_t)v.m * v.n;
     }
     if (toff >= ((int64_t)1 << 31)) {
@@ -318,6 +384,17 @@ int mandel_plan_create(const mandel_view *views, int32_t nviews, const mandel_tu
                       hipMemcpyHostToDevice);
     if (e == hipSuccess)
         e = hipMalloc((void **)&p->d_head, HEAD_BYTES);
+    if (e == hipSuccess && !ytab.empty()) {
+        e = hipMalloc((void **)&p->d_ytab, sizeof(double) * ytab.size());
+        if (e == hipSuccess)
+            e = hipMemcpy(p->d_ytab, ytab.data(), sizeof(double) * ytab.size(),
+                          hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = hipMalloc((void **)&p->d_rmap, sizeof(int32_t) * rmap.size());
+        if (e == hipSuccess)
+            e = hipMemcpy(p->d_rmap, rmap.data(), sizeof(int32_t) * rmap.size(),
+                          hipMemcpyHostToDevice);
+    }
     if (e == hipSuccess)
         e = hipStreamCreateWithFlags(&p->capture, hipStreamNonBlocking);
     if (e != hipSuccess) {
@@ -376,6 +453,9 @@ int mandel_plan_launch(mandel_plan *p, int32_t *out, const mandel_launch *args, 
         return fail(MANDEL_EINVAL, "probe_cap=%d outside [-2^20, 2^20]", la.probe_cap);
     if (la.first_slot < 0)
         return fail(MANDEL_EINVAL, "negative first_slot");
+    if (la.first_slot != 0 && !p->expands.empty())
+        return fail(MANDEL_EINVAL, "first_slot must be 0 on a plan with collapsed rows (the "
+                                   "row copies after the render would overwrite skipped rows)");
     if (la.periodicity != 0 && la.periodicity != 1)
         return fail(MANDEL_EINVAL, "periodicity must be 0 or 1");
     if (la.reserved != 0)
@@ -469,7 +549,7 @@ int mandel_plan_features(mandel_plan *p, float *feat, int32_t probe_cap, void *s
         return MANDEL_OK;
     if (!feat)
         return fail(MANDEL_EINVAL, "feat is NULL");
-    hipError_t e = launch_features(p->d_views, (int32_t)p->views.size(), p->ntiles,
+    hipError_t e = launch_features(p->d_views, (int32_t)p->views.size(), p->d_ytab, p->ntiles,
                                    p->tune.tile_w, p->tune.tile_h, probe_cap, feat,
                                    (hipStream_t)stream);
     return e == hipSuccess ? MANDEL_OK : hip_fail(e, "features launch");
@@ -497,6 +577,8 @@ int mandel_plan_destroy(mandel_plan *p)
     (void)hipFree(p->d_hist);
     (void)hipFree(p->d_chunk);
     (void)hipFree(p->d_active);
+    (void)hipFree(p->d_ytab);
+    (void)hipFree(p->d_rmap);
     delete p;
     return MANDEL_OK;
 }

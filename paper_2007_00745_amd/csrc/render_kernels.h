@@ -27,7 +27,9 @@ struct ViewDesc {
     int32_t max_iter;
     int32_t tiles_x;         // tiles per tile-row
     int32_t tiles_y;
-    int32_t pad;
+    int32_t ytab_off;        // -1: row i has cy = cy0 + ((i + 0.5) - m/2) dy; >= 0: the
+                             // view's rows are the distinct row coordinates of a larger
+                             // view (collapsed rows), row i's cy = ytab[ytab_off + i]
     int64_t row_off;         // batch row policies: index of this view's first row in the
                              // concatenation of all views' rows
 };
@@ -45,6 +47,7 @@ struct RenderArgs {
     int32_t parts;                 // queue items per tile (row parts), >= 1; 1 for GRID
     int64_t first_slot;            // FCFS / ORDERED: the queue starts at this slot
     int64_t nrows;                 // batch row policies: rows of all views together
+    const double *ytab;            // row coordinates of views with collapsed rows, or NULL
     int32_t *out;                  // output base
     unsigned long long *head;      // queue head (FCFS / ORDERED)
     const int32_t *order;          // ORDERED: queue slot -> tile id
@@ -75,5 +78,9 @@ hipError_t launch_clear(unsigned long long *head, int64_t first_slot, int64_t *t
                         hipStream_t s, int32_t *chunk = nullptr, int32_t *active = nullptr,
                         int64_t nwaves = 0);
 int persistent_blocks_per_cu(int policy, bool batch, int tests, int threads);
+// Copies whole rows inside one view's image: row i of [lo, hi) becomes a copy of row
+// rmap[i] (rmap[i] < lo for every such i), n columns per row.
+hipError_t launch_expand_rows(int32_t *img, int64_t n, const int32_t *rmap, int32_t lo, int32_t hi,
+                              hipStream_t s);
 
 } // namespace mandel

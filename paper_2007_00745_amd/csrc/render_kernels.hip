@@ -122,7 +122,7 @@ __device__ __forceinline__ ViewDesc load_view(const __attribute__((address_space
     d.max_iter = p->max_iter;
     d.tiles_x = p->tiles_x;
     d.tiles_y = p->tiles_y;
-    d.pad = p->pad;
+    d.ytab_off = p->ytab_off;
     d.row_off = p->row_off;
     return d;
 }
@@ -575,11 +575,15 @@ render_kernel(RenderArgs a)
                 i += s_y0;
                 j += s_x0;
                 const double offx = ((double)j + 0.5) - 0.5 * (double)vd->n;
-                const double offy = ((double)i + 0.5) - 0.5 * (double)vd->m;
                 const double px = offx * vd->dx;
-                const double py = offy * vd->dy;
                 cx = vd->cx0 + px;
-                cy = vd->cy0 + py;
+                if (BATCH && vd->ytab_off >= 0) {
+                    cy = a.ytab[vd->ytab_off + i];
+                } else {
+                    const double offy = ((double)i + 0.5) - 0.5 * (double)vd->m;
+                    const double py = offy * vd->dy;
+                    cy = vd->cy0 + py;
+                }
                 x = 0.0;
                 y = 0.0;
                 if constexpr (BATCH)
@@ -936,6 +940,48 @@ hipError_t launch_render(const RenderArgs &a, int policy, bool batch, int tests,
     default:
         return hipErrorInvalidValue;
     }
+}
+
+// Rows [lo, hi) of an image of n columns become copies of rows rmap[i] < lo; 16-byte
+// vectors when the rows are 16-byte aligned.
+__global__ void expand_rows_kernel(int32_t *img, int64_t n, const int32_t *rmap, int32_t lo,
+                                   int32_t hi)
+{
+    const int32_t i = lo + (int32_t)blockIdx.y;
+    if (i >= hi)
+        return;
+    const int32_t src = rmap[i];
+    int32_t *dst = img + (int64_t)i * n;
+    const int32_t *from = img + (int64_t)src * n;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    if ((n & 3) == 0 && (((uintptr_t)img) & 15) == 0) {
+        const int64_t n4 = n >> 2;
+        for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n4; q += stride)
+            ((int4 *)dst)[q] = ((const int4 *)from)[q];
+    } else {
+        for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += stride)
+            dst[q] = from[q];
+    }
+}
+
+hipError_t launch_expand_rows(int32_t *img, int64_t n, const int32_t *rmap, int32_t lo, int32_t hi,
+                              hipStream_t s)
+{
+    if (hi <= lo || n <= 0)
+        return hipSuccess;
+    const int64_t per_row = (n + 4 * 256 - 1) / (4 * 256);
+    const unsigned gx = (unsigned)(per_row < 64 ? per_row : 64);
+    const unsigned rows = (unsigned)(hi - lo);
+    // grid.y is limited to 65535 rows per launch
+    for (unsigned r0 = 0; r0 < rows; r0 += 65535u) {
+        const unsigned nr = rows - r0 < 65535u ? rows - r0 : 65535u;
+        hipLaunchKernelGGL(expand_rows_kernel, dim3(gx, nr), dim3(256), 0, s, img, n, rmap,
+                           lo + (int32_t)r0, lo + (int32_t)(r0 + nr));
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess)
+            return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_clear(unsigned long long *head, int64_t first_slot, int64_t *tile_cost,

@@ -65,7 +65,7 @@ class Tuning(ctypes.Structure):
                 ("grain", ctypes.c_int32), ("waves_per_group", ctypes.c_int32),
                 ("block_iters", ctypes.c_int32), ("young_iters", ctypes.c_int32),
                 ("groups", ctypes.c_int32), ("refill_lanes", ctypes.c_int32),
-                ("tile_parts", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("tile_parts", ctypes.c_int32), ("collapse_rows", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         return {k: int(getattr(self, k)) for k, _ in self._fields_ if k != "reserved"}

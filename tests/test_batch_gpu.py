@@ -484,3 +484,79 @@ def test_binding_rejects_wrong_buffers(small_batch):
     with pytest.raises(ValueError):
         native.order_desc(torch.zeros(10, dtype=torch.float64, device="cuda"))
     plan.close()
+
+
+def _collapsing_views():
+    # view 0: a boundary zoom whose row pitch (1e-17) is far below the spacing of doubles
+    # near its imaginary part (about 1.1e-16), so about 11 neighbouring rows share each
+    # row coordinate; view 1 likewise with ragged sizes against 64x8 tiles; view 2 an
+    # ordinary zoom (nothing to collapse); view 3 empty; view 4 a single row
+    cx, cy = workloads.boundary_centre(745, 0)
+    return [workloads.View((cx, cy, 2e-15, 1e-17), 157, 96, 2000),
+            workloads.View((cx, cy + 3e-15, 3e-15, 2.5e-17), 61, 70, 900),
+            workloads.View((-0.745, 0.113, 1e-4, 1e-4), 45, 130, 700),
+            workloads.View((0.3, 0.1, 0.1, 0.1), 0, 9, 50),
+            workloads.View((cx, cy, 1e-15, 1e-17), 1, 33, 400)]
+
+
+def _distinct_rows(v):
+    # the row coordinates as the kernels form them, and the first row of each value
+    i = np.arange(v.m, dtype=np.float64)
+    cy = v.window[1] + ((i + 0.5) - v.m / 2.0) * v.window[3]
+    first = np.concatenate([[True], cy[1:] != cy[:-1]]) if v.m else np.zeros(0, bool)
+    return cy, first
+
+
+@pytest.mark.parametrize("mode", ["fcfs", "probe", "learned", "ordered", "static",
+                                  "alternating"])
+@pytest.mark.parametrize("use_graph", [False, True])
+def test_collapsed_rows_match_the_oracle(mode, use_graph):
+    views = _collapsing_views()
+    want = [oracle.render(v.window, v.m, v.n, v.max_iter, v.R) for v in views]
+    flat = native.Plan(views)
+    plan = native.Plan(views, {"collapse_rows": 1})
+    assert plan.tuning["collapse_rows"] == 1
+    distinct = [int(_distinct_rows(v)[1].sum()) for v in views]
+    assert distinct[0] < views[0].m // 5 and distinct[2] == views[2].m
+    assert plan.ntiles < flat.ntiles
+    kw = {}
+    if mode == "learned":
+        kw["mlp"] = torch.tensor(_params(5), dtype=torch.float32, device="cuda")
+    elif mode == "ordered":
+        kw["order"] = torch.randperm(plan.ntiles, device="cuda").to(torch.int32)
+    elif mode in ("static", "alternating"):
+        kw["workers"] = 37
+    out = torch.full((plan.out_size(),), -1, dtype=torch.int32, device="cuda")
+    cost = None if mode in ("static", "alternating") else torch.empty(
+        plan.ntiles, dtype=torch.int64, device="cuda")
+    for rep in range(3):
+        out.fill_(-1)
+        plan.launch(out, mode=mode, use_graph=use_graph, tile_cost=cost, **kw)
+        torch.cuda.synchronize()
+        _check(plan, out, want)
+    if cost is not None:
+        # the tile costs cover each distinct row once
+        rendered = sum(int(w[_distinct_rows(v)[1]].sum()) for v, w in zip(views, want))
+        assert int(cost.sum().item()) == rendered
+    plan.close()
+    flat.close()
+
+
+def test_collapsed_rows_refuse_a_resumed_queue():
+    views = _collapsing_views()
+    plan = native.Plan(views, {"collapse_rows": 1})
+    out = torch.full((plan.out_size(),), -1, dtype=torch.int32, device="cuda")
+    with pytest.raises(native.MandelError):
+        plan.launch(out, first_slot=1)
+    torch.cuda.synchronize()
+    assert int(out.max().item()) == -1
+    plan.close()
+    # views whose rows are all distinct are rendered as without the option
+    plain = [workloads.c1()]
+    p = native.Plan(plain, {"collapse_rows": 1})
+    assert p.ntiles == native.Plan(plain).ntiles
+    out = torch.full((p.out_size(),), -1, dtype=torch.int32, device="cuda")
+    p.launch(out, first_slot=0)
+    torch.cuda.synchronize()
+    _check(p, out, [oracle.render(plain[0].window, 480, 640, 1000, 2.0)])
+    p.close()

@@ -165,3 +165,12 @@ def test_empty_image_needs_no_order():
     assert _call(m=0, out=None, sched=sched) == native.OK
     assert _call(n=0, out=None, sched=sched) == native.OK
     assert _call(sched=sched) == native.EINVAL   # a real image still needs its order
+
+
+def test_plan_rejects_bad_collapse_flag():
+    v = native.ViewC(native.Window(-0.5, 0.0, 0.01, 0.01), 8, 8, 10, 0, 2.0, 0)
+    arr = (native.ViewC * 1)(v)
+    t = native.Tuning(collapse_rows=2)
+    h = ctypes.c_void_p()
+    assert native.lib().mandel_plan_create(arr, 1, ctypes.byref(t), ctypes.byref(h)) == native.EINVAL
+    assert b"collapse_rows" in native.lib().mandel_last_error()
