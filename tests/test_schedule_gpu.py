@@ -170,6 +170,16 @@ def test_stress_batch_c5():
         for a in range(0, flat.size, step):
             h.update(np.ascontiguousarray(flat[a:a + step], dtype="<i4").tobytes())
         assert h.hexdigest() == g["sha256"]
+    # the benchmark's collapsed-rows plan (the deep view's rows share imaginary parts in
+    # binary64) gives the same image in full, with fewer rendered rows
+    cplan = native.Plan(views, {"block_iters": 128, "collapse_rows": 1})
+    assert cplan.ntiles < plan.ntiles
+    cout = torch.full((cplan.out_size(),), -1, dtype=torch.int32, device="cuda")
+    cplan.launch(cout, use_graph=True)
+    torch.cuda.synchronize()
+    assert torch.equal(cout, out)
+    cplan.close()
+    del cout
     plan.close()
 
 
