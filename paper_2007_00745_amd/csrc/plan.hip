@@ -4,6 +4,7 @@
 // include/mandel.h.
 #include <hip/hip_runtime.h>
 
+#include <climits>
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -292,8 +293,8 @@ int enqueue(mandel_plan *p, int32_t *out, const mandel_launch &la, hipStream_t s
 // and afterwards copied out: row i becomes a copy of rendered row rmap[i] <= i.  The
 // copies run in passes over ranges [lo, hi) whose sources all lie below lo, from the
 // bottom of the image up, so no pass reads a row that a pass has already written.
-void collapse_rows(mandel_plan *p, int32_t k, std::vector<double> &ytab,
-                   std::vector<int32_t> &rmap)
+int collapse_rows(mandel_plan *p, int32_t k, std::vector<double> &ytab,
+                  std::vector<int32_t> &rmap)
 {
     ViewDesc &d = p->views[(size_t)k];
     const int32_t m = d.m;
@@ -308,7 +309,10 @@ void collapse_rows(mandel_plan *p, int32_t k, std::vector<double> &ytab,
         map[(size_t)i] = (int32_t)ys.size() - 1;
     }
     if ((int32_t)ys.size() == m)
-        return; // every row distinct
+        return MANDEL_OK; // every row distinct
+    if ((int64_t)ytab.size() + (int64_t)ys.size() > INT32_MAX ||
+        (int64_t)rmap.size() + m > ((int64_t)1 << 40))
+        return fail(MANDEL_EINVAL, "view %d: too many collapsed rows in one plan", k);
     d.ytab_off = (int32_t)ytab.size();
     ytab.insert(ytab.end(), ys.begin(), ys.end());
     const int64_t rmap_off = (int64_t)rmap.size();
@@ -322,6 +326,7 @@ void collapse_rows(mandel_plan *p, int32_t k, std::vector<double> &ytab,
         p->expands.push_back({k, rmap_off, lo, hi});
         hi = lo;
     }
+    return MANDEL_OK;
 }
 
 } // namespace
@@ -362,8 +367,13 @@ int mandel_plan_create(const mandel_view *views, int32_t nviews, const mandel_tu
         }
         ViewDesc &d = p->views[k];
         d.out_off = v.out_offset;
-        if (tu.collapse_rows && v.m > 1 && v.n > 0)
-            collapse_rows(p, k, ytab, rmap);
+        if (tu.collapse_rows && v.m > 1 && v.n > 0) {
+            rc = collapse_rows(p, k, ytab, rmap);
+            if (rc) {
+                delete p;
+                return rc;
+            }
+        }
         d.tile_off = toff;
         d.row_off = p->nrows;
         toff += tile_count(d.m, d.n, tu.tile_w, tu.tile_h);
