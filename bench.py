@@ -702,9 +702,10 @@ def stress_batch(torch, native, workloads, costmodel, reps: int, clock_khz: floa
     return res
 
 
-def comparisons(torch, native, view, plan, out, cost, sum_counts, stream) -> dict:
+def comparisons(torch, native, view, plan, out, cost, sum_counts, stream, params=None) -> dict:
     """The plain mandel_render (FCFS in tile order) and the true-cost order on the
-    headline view, and the cost of the probe features alone."""
+    headline view, the cost of the probe features alone, and the time to the image with
+    conjugate rows rendered once (the learned step's order when a model is given)."""
     comp = {}
     plain = torch.empty((view.m, view.n), dtype=torch.int32, device="cuda")
     comp["plain_fcfs_render_ms"] = timed_ms(
@@ -718,6 +719,28 @@ def comparisons(torch, native, view, plan, out, cost, sum_counts, stream) -> dic
     comp["features_ms"] = timed_ms(torch, lambda: plan.features(stream=stream), 3, "features")
     for k in ("plain_fcfs_render_ms", "true_cost_order_ms"):
         comp[k.replace("_ms", "_pixel_iterations_per_s")] = sum_counts / (comp[k] / 1e3)
+    # Time to the same image when rows that are conjugates of each other are rendered
+    # once (the window is centred on the real axis, and conjugate points have equal
+    # counts bit for bit): half the rows run, then they are copied.  Reported apart;
+    # the headline counts every executed iteration of the whole image.
+    ref = out.clone()
+    mplan = native.Plan([view], {"collapse_rows": 2})
+    mcost = torch.empty(mplan.ntiles, dtype=torch.int64, device="cuda")
+    out.fill_(-1)
+    mplan.launch(out, tile_cost=mcost, stream=stream)
+    torch.cuda.synchronize()
+    assert torch.equal(out, ref), "mirrored rows changed the counts"
+    executed = int(mcost.sum().item())
+    out.fill_(-1)
+    mkw = {"mode": "learned", "mlp": params} if params is not None else {}
+    t = timed_ms(torch, lambda: mplan.launch(out, use_graph=True, stream=stream, **mkw), 3,
+                 "mirrored rows")
+    assert torch.equal(out, ref), "mirrored rows changed the counts"
+    comp["mirrored_rows"] = {"ms": t, "mode": "learned" if mkw else "fcfs", "tiles": mplan.ntiles,
+                             "iterations_executed": executed,
+                             "executed_iterations_per_s": executed / (t / 1e3),
+                             "time_to_image_speedup_vs_fcfs": comp["plain_fcfs_render_ms"] / t}
+    mplan.close()
     return comp
 
 
@@ -986,7 +1009,7 @@ def main():
         ceiling["render_frac_of_clock_adjusted_peak"] = render_tflops / ceiling["fma_chain"]["tflops"]
         log(f"bench: fp64 ceilings fma {ceiling['fma_chain']['tflops']:.1f}, update loop "
             f"{best:.1f} TFLOP/s")
-        comp = comparisons(torch, native, view, plan, out, cost, sum_counts, stream)
+        comp = comparisons(torch, native, view, plan, out, cost, sum_counts, stream, params)
         comp["paper_partitions_one_view"] = view_partitions(
             torch, native, view, out.clone(), sum_counts, int(dinfo["compute_units"]),
             clock_khz, ms_mean)

@@ -280,14 +280,18 @@ typedef struct mandel_tuning {
                                 view's pitch dy lies below the spacing of doubles near
                                 its centre, neighbouring rows get the same imaginary part
                                 (cy0 + ((i + 0.5) - m/2) dy rounds to equal values) and so
-                                the same counts.  Such a view is rendered as one row per
-                                distinct value into the first rows of its image, and the
-                                rows are then copied to their places (extra kernels after
-                                the render, in the same launch).  The image is identical;
-                                tile ids, tile costs, features, statistics and the row
-                                partitions (STATIC_ROWS / ALTERNATING_ROWS) then refer to
-                                the collapsed rows, and first_slot must be 0.  Views
-                                whose rows are all distinct are unchanged.  0: off [0] */
+                                the same counts.  2: also merge rows whose imaginary parts
+                                differ only in sign (conjugate points have equal counts,
+                                bit for bit; a window centred on the real axis renders
+                                half its rows).  A view with merged rows is rendered as
+                                one row per distinct value into the first rows of its
+                                image, and the rows are then copied to their places
+                                (extra kernels after the render, in the same launch).
+                                The image is identical; tile ids, tile costs, features,
+                                statistics and the row partitions (STATIC_ROWS /
+                                ALTERNATING_ROWS) then refer to the rendered rows, and
+                                first_slot must be 0.  Views whose rows are all distinct
+                                are unchanged.  0: off [0] */
 } mandel_tuning;
 
 typedef struct mandel_plan mandel_plan;

@@ -7,6 +7,8 @@
 #include <climits>
 #include <cmath>
 #include <cstring>
+#include <algorithm>
+#include <unordered_map>
 #include <vector>
 
 #include "costmodel.h"
@@ -104,8 +106,8 @@ int fill_tuning(const mandel_tuning *t, mandel_tuning *o)
     d.refill_lanes = c.refill_lanes;
     d.tile_parts = c.tile_parts;
     d.groups = c.workers;
-    if (d.collapse_rows != 0 && d.collapse_rows != 1)
-        return fail(MANDEL_EINVAL, "collapse_rows must be 0 or 1");
+    if (d.collapse_rows < 0 || d.collapse_rows > 2)
+        return fail(MANDEL_EINVAL, "collapse_rows must be 0, 1 or 2");
     *o = d;
     return MANDEL_OK;
 }
@@ -286,27 +288,38 @@ int enqueue(mandel_plan *p, int32_t *out, const mandel_launch &la, hipStream_t s
 }
 
 // Collapsed rows.  Row i of view k has imaginary part cy0 + ((i + 0.5) - m/2) dy (one
-// rounded product, one rounded sum, exactly as the kernels form it); when dy is below
-// the spacing of doubles near cy0, neighbouring rows round to the same value, and rows
-// with equal c have equal counts.  Such a view is rendered as m' <= m rows, one per
-// distinct value (kept in ytab, in row order), into the first m' rows of its image,
-// and afterwards copied out: row i becomes a copy of rendered row rmap[i] <= i.  The
-// copies run in passes over ranges [lo, hi) whose sources all lie below lo, from the
-// bottom of the image up, so no pass reads a row that a pass has already written.
-int collapse_rows(mandel_plan *p, int32_t k, std::vector<double> &ytab,
+// rounded product, one rounded sum, exactly as the kernels form it).  Rows with the
+// same c have the same counts: when dy is below the spacing of doubles near cy0,
+// neighbouring rows round to the same value.  Conjugate points have the same counts
+// too, bit for bit (rounding to nearest is symmetric in sign, so the orbit of the
+// conjugate is the conjugate orbit), so with mirror set rows whose imaginary parts
+// differ only in sign are merged as well.  Such a view is rendered as m' <= m rows, one
+// per distinct key in order of first occurrence (the first row's cy kept in ytab),
+// into the first m' rows of its image, and afterwards copied out: row i takes
+// rendered row rmap[i] <= i.  The copies run in passes over ranges [lo, hi) whose
+// sources all lie below lo, from the bottom of the image up; a row is overwritten only
+// after every row that copies it has been written, so the copies run in place.
+int collapse_rows(mandel_plan *p, int32_t k, bool mirror, std::vector<double> &ytab,
                   std::vector<int32_t> &rmap)
 {
     ViewDesc &d = p->views[(size_t)k];
     const int32_t m = d.m;
     std::vector<double> ys;
     std::vector<int32_t> map((size_t)m);
+    std::unordered_map<uint64_t, int32_t> seen;
     for (int32_t i = 0; i < m; ++i) {
         const double off = ((double)i + 0.5) - 0.5 * (double)m;
         const double py = off * d.dy;
         const double cy = d.cy0 + py;
-        if (ys.empty() || cy != ys.back())
+        const double key = mirror ? std::fabs(cy) : cy + 0.0; // + 0.0: -0 and +0 alike
+        uint64_t bits;
+        std::memcpy(&bits, &key, sizeof bits);
+        auto it = seen.find(bits);
+        if (it == seen.end()) {
+            it = seen.emplace(bits, (int32_t)ys.size()).first;
             ys.push_back(cy);
-        map[(size_t)i] = (int32_t)ys.size() - 1;
+        }
+        map[(size_t)i] = it->second;
     }
     if ((int32_t)ys.size() == m)
         return MANDEL_OK; // every row distinct
@@ -319,10 +332,20 @@ int collapse_rows(mandel_plan *p, int32_t k, std::vector<double> &ytab,
     rmap.insert(rmap.end(), map.begin(), map.end());
     d.m = (int32_t)ys.size();
     d.tiles_y = (int32_t)(((int64_t)d.m + p->tune.tile_h - 1) / p->tune.tile_h);
+    // Passes, top down.  A row with map[i] == i holds its own rendered row and stays.
+    // Otherwise the pass takes rows downward from hi - 1 while every source of the
+    // pass stays below its lowest row (map[i] <= i, so row hi - 1 alone qualifies).
     for (int32_t hi = m; hi > 0;) {
-        const int32_t lo = map[(size_t)hi - 1] + 1;
-        if (lo >= hi)
-            break; // rows below hi are all distinct: rendered in place
+        if (map[(size_t)hi - 1] == hi - 1) {
+            --hi;
+            continue;
+        }
+        int32_t lo = hi - 1, top = map[(size_t)hi - 1];
+        while (lo > 0 && map[(size_t)lo - 1] != lo - 1 &&
+               std::max(top, map[(size_t)lo - 1]) < lo - 1) {
+            top = std::max(top, map[(size_t)lo - 1]);
+            --lo;
+        }
         p->expands.push_back({k, rmap_off, lo, hi});
         hi = lo;
     }
@@ -368,7 +391,7 @@ int mandel_plan_create(const mandel_view *views, int32_t nviews, const mandel_tu
         ViewDesc &d = p->views[k];
         d.out_off = v.out_offset;
         if (tu.collapse_rows && v.m > 1 && v.n > 0) {
-            rc = collapse_rows(p, k, ytab, rmap);
+            rc = collapse_rows(p, k, tu.collapse_rows == 2, ytab, rmap);
             if (rc) {
                 delete p;
                 return rc;

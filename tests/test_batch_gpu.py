@@ -491,33 +491,46 @@ def _collapsing_views():
     # near its imaginary part (about 1.1e-16), so about 11 neighbouring rows share each
     # row coordinate; view 1 likewise with ragged sizes against 64x8 tiles; view 2 an
     # ordinary zoom (nothing to collapse); view 3 empty; view 4 a single row
+    # (ordinary for rows that merge by value); views 5 and 6 are centred on the real
+    # axis (even and odd row counts), so their rows pair up by conjugation
     cx, cy = workloads.boundary_centre(745, 0)
     return [workloads.View((cx, cy, 2e-15, 1e-17), 157, 96, 2000),
             workloads.View((cx, cy + 3e-15, 3e-15, 2.5e-17), 61, 70, 900),
             workloads.View((-0.745, 0.113, 1e-4, 1e-4), 45, 130, 700),
             workloads.View((0.3, 0.1, 0.1, 0.1), 0, 9, 50),
-            workloads.View((cx, cy, 1e-15, 1e-17), 1, 33, 400)]
+            workloads.View((cx, cy, 1e-15, 1e-17), 1, 33, 400),
+            workloads.View(workloads.window_from_bounds(-2.0, 1.0, -1.2, 1.2, 96, 120), 96,
+                           120, 600),
+            workloads.View((-0.75, 0.0, 1e-3, 1e-3), 37, 81, 1500)]
 
 
-def _distinct_rows(v):
+def _distinct_rows(v, mirror=False):
     # the row coordinates as the kernels form them, and the first row of each value
+    # (of each absolute value with mirror)
     i = np.arange(v.m, dtype=np.float64)
     cy = v.window[1] + ((i + 0.5) - v.m / 2.0) * v.window[3]
-    first = np.concatenate([[True], cy[1:] != cy[:-1]]) if v.m else np.zeros(0, bool)
+    key = np.abs(cy) if mirror else cy
+    _, idx = np.unique(key, return_index=True)
+    first = np.zeros(v.m, bool)
+    first[idx] = True
     return cy, first
 
 
 @pytest.mark.parametrize("mode", ["fcfs", "probe", "learned", "ordered", "static",
                                   "alternating"])
 @pytest.mark.parametrize("use_graph", [False, True])
-def test_collapsed_rows_match_the_oracle(mode, use_graph):
+@pytest.mark.parametrize("collapse", [1, 2])
+def test_collapsed_rows_match_the_oracle(mode, use_graph, collapse):
     views = _collapsing_views()
     want = [oracle.render(v.window, v.m, v.n, v.max_iter, v.R) for v in views]
     flat = native.Plan(views)
-    plan = native.Plan(views, {"collapse_rows": 1})
-    assert plan.tuning["collapse_rows"] == 1
-    distinct = [int(_distinct_rows(v)[1].sum()) for v in views]
+    plan = native.Plan(views, {"collapse_rows": collapse})
+    assert plan.tuning["collapse_rows"] == collapse
+    mirror = collapse == 2
+    distinct = [int(_distinct_rows(v, mirror)[1].sum()) for v in views]
     assert distinct[0] < views[0].m // 5 and distinct[2] == views[2].m
+    if mirror:
+        assert distinct[5] == 48 and distinct[6] == 19
     assert plan.ntiles < flat.ntiles
     kw = {}
     if mode == "learned":
@@ -536,7 +549,7 @@ def test_collapsed_rows_match_the_oracle(mode, use_graph):
         _check(plan, out, want)
     if cost is not None:
         # the tile costs cover each distinct row once
-        rendered = sum(int(w[_distinct_rows(v)[1]].sum()) for v, w in zip(views, want))
+        rendered = sum(int(w[_distinct_rows(v, mirror)[1]].sum()) for v, w in zip(views, want))
         assert int(cost.sum().item()) == rendered
     plan.close()
     flat.close()

@@ -170,7 +170,7 @@ def test_empty_image_needs_no_order():
 def test_plan_rejects_bad_collapse_flag():
     v = native.ViewC(native.Window(-0.5, 0.0, 0.01, 0.01), 8, 8, 10, 0, 2.0, 0)
     arr = (native.ViewC * 1)(v)
-    t = native.Tuning(collapse_rows=2)
+    t = native.Tuning(collapse_rows=3)
     h = ctypes.c_void_p()
     assert native.lib().mandel_plan_create(arr, 1, ctypes.byref(t), ctypes.byref(h)) == native.EINVAL
     assert b"collapse_rows" in native.lib().mandel_last_error()
