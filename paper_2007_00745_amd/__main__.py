@@ -12,6 +12,10 @@ The window is given by its bounds (re_min re_max im_min im_max) or by its centre
 pixel pitch.  --schedule picks the work partition: fcfs (device queue, default),
 static or alternating rows over --workers workgroups (paper Sec. III-A, III-C).
 With --periodicity the FCFS render runs from a one-view plan with row stealing.
+--collapse-rows 1 renders rows that share their imaginary part in binary64 once (deep
+zooms below binary64 resolution), 2 also rows that are conjugates of each other (a
+window centred on the real axis); the image is the same, and the executed iterations
+are reported apart from the image's sum of counts.
 """
 from __future__ import annotations
 
@@ -39,6 +43,9 @@ def main(argv=None) -> int:
                     help="longest block of untested updates (default 1024, and 128 with "
                          "--periodicity: a cycle is found one block after the orbit reaches "
                          "it, so shorter blocks find it sooner)")
+    ap.add_argument("--collapse-rows", type=int, choices=(0, 1, 2), default=0,
+                    help="render rows with equal (1) or equal and opposite (2) imaginary "
+                         "parts once, then copy them (same image)")
     ap.add_argument("--double-double", action="store_true",
                     help="double-double arithmetic for pitches below binary64 resolution")
     ap.add_argument("--out", default="mandelbrot.ppm")
@@ -55,8 +62,12 @@ def main(argv=None) -> int:
     else:
         b = args.bounds or (-2.0, 1.0, -1.2, 1.2)
         cx, cy, dx, dy = workloads.window_from_bounds(b[0], b[1], b[2], b[3], m, n)
-    if args.double_double and (args.schedule != "fcfs" or args.periodicity):
-        ap.error("--double-double uses the FCFS queue without periodicity detection")
+    if args.double_double and (args.schedule != "fcfs" or args.periodicity or
+                               args.collapse_rows):
+        ap.error("--double-double uses the FCFS queue without periodicity detection or "
+                 "collapsed rows")
+    if args.collapse_rows and args.schedule != "fcfs":
+        ap.error("--collapse-rows renders from a one-view plan with the FCFS queue")
     if args.schedule != "fcfs" and args.workers < 1:
         args.workers = m
 
@@ -65,16 +76,20 @@ def main(argv=None) -> int:
     a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     native.lib()
     plan = None
-    if args.periodicity and args.schedule == "fcfs":
-        # a one-view plan, for row stealing: the tiles whose orbits never settle on a
-        # short cycle are the tail, and stealing spreads their rows over idle wavefronts
+    if (args.periodicity or args.collapse_rows) and args.schedule == "fcfs":
+        # a one-view plan: for row stealing (the tiles whose orbits never settle on a
+        # short cycle are the tail, and stealing spreads their rows over idle wavefronts)
+        # and for collapsed rows
         plan = native.Plan([workloads.View((cx, cy, dx, dy), m, n, args.max_iter, args.radius)],
-                           {"block_iters": args.block_iters or 128})
+                           {"block_iters": args.block_iters or (128 if args.periodicity
+                                                                else 1024),
+                            "collapse_rows": args.collapse_rows})
     torch.cuda.synchronize()  # device, library and plan set-up stay outside the timed part
     t0 = time.perf_counter()
     a.record()
     if plan is not None:
-        plan.launch(out.view(-1), periodicity=1, steal=1, stats=stats)
+        per = int(args.periodicity)
+        plan.launch(out.view(-1), periodicity=per, steal=per, stats=stats)
     elif args.double_double:
         native.render_dd((cx, 0.0, cy, 0.0, dx, dy), m, n, args.max_iter, args.radius, out=out,
                          stats=stats)
@@ -93,11 +108,14 @@ def main(argv=None) -> int:
         plan.close()
     counts = int(out.sum(dtype=torch.int64).item())
     skipped = 0 if args.double_double else int(stats[7].item())
+    # counts of the rendered pixels (all of them unless rows were collapsed), less the
+    # updates that periodicity detection skipped
+    executed = int(stats[1].item()) - skipped
     compute_ms = a.elapsed_time(b)
     print(json.dumps({"file": args.out, "rows": m, "cols": n, "max_iter": args.max_iter,
                       "sum_counts": counts, "updates_skipped": skipped,
-                      "compute_ms": compute_ms,
-                      "executed_pixel_iterations_per_s": (counts - skipped) / (compute_ms / 1e3),
+                      "iterations_executed": executed, "compute_ms": compute_ms,
+                      "executed_pixel_iterations_per_s": executed / (compute_ms / 1e3),
                       "total_s_including_write": total}))
     return 0
 

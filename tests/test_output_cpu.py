@@ -70,3 +70,9 @@ def test_cli_argument_errors():
         cli.main(["--centre", "0", "0"])                      # no pitch
     with pytest.raises(SystemExit):
         cli.main(["--double-double", "--schedule", "static"])
+    with pytest.raises(SystemExit):
+        cli.main(["--double-double", "--collapse-rows", "1"])
+    with pytest.raises(SystemExit):
+        cli.main(["--collapse-rows", "2", "--schedule", "alternating"])
+    with pytest.raises(SystemExit):
+        cli.main(["--collapse-rows", "3"])
