@@ -284,9 +284,11 @@ typedef struct mandel_tuning {
                                 differ only in sign (conjugate points have equal counts,
                                 bit for bit; a window centred on the real axis renders
                                 half its rows).  A view with merged rows is rendered as
-                                one row per distinct value into the first rows of its
-                                image, and the rows are then copied to their places
-                                (extra kernels after the render, in the same launch).
+                                one row per distinct value, each into the image row where
+                                the value first occurs, and every other row is then copied
+                                from that row (one more kernel per such view after the
+                                render, in the same launch).  At most 2^28 rendered and
+                                2^28 copied rows over the collapsed views of a plan.
                                 The image is identical; tile ids, tile costs, features,
                                 statistics and the row partitions (STATIC_ROWS /
                                 ALTERNATING_ROWS) then refer to the rendered rows, and

@@ -191,7 +191,7 @@ int make_view(const mandel_window *w, int32_t m, int32_t n, int32_t max_iter, do
     d->max_iter = max_iter;
     d->tiles_x = (int32_t)(((int64_t)n + tile_w - 1) / tile_w);
     d->tiles_y = (int32_t)(((int64_t)m + tile_h - 1) / tile_h);
-    d->ytab_off = -1;
+    d->rows_off = -1;
     return MANDEL_OK;
 }
 

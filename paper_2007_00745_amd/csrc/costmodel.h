@@ -8,7 +8,7 @@
 
 namespace mandel {
 
-hipError_t launch_features(const ViewDesc *views, int32_t nviews, const double *ytab,
+hipError_t launch_features(const ViewDesc *views, int32_t nviews, const RowRef *rows,
                            int64_t ntiles, int32_t tile_w, int32_t tile_h, int32_t probe_cap,
                            float *feat, hipStream_t s);
 hipError_t launch_probe_key(const float *feat, int64_t ntiles, int32_t probe_cap, float *keys,

@@ -62,7 +62,7 @@ constexpr int32_t PROBE_BLOCK = 16;  // updates per untested block
 constexpr int32_t PROBE_REPLAYS = 2; // replays before a wave tests every update
 
 __global__ void __launch_bounds__(256) features_kernel(const ViewDesc *views, int32_t nviews,
-                                                       const double *ytab, int64_t ntiles,
+                                                       const RowRef *rows, int64_t ntiles,
                                                        int32_t tile_w, int32_t tile_h,
                                                        int32_t probe_cap, float *feat)
 {
@@ -89,8 +89,8 @@ __global__ void __launch_bounds__(256) features_kernel(const ViewDesc *views, in
     const double px = offx * vd.dx;
     const double cx = vd.cx0 + px;
     double cy;
-    if (vd.ytab_off >= 0) { // collapsed rows: the row's coordinate from the plan's table
-        cy = ytab[vd.ytab_off + i];
+    if (vd.rows_off >= 0) { // collapsed rows: the row's coordinate from the plan's table
+        cy = rows[vd.rows_off + i].cy;
     } else {
         const double offy = ((double)i + 0.5) - 0.5 * (double)vd.m;
         const double py = offy * vd.dy;
@@ -157,8 +157,8 @@ __global__ void __launch_bounds__(256) features_kernel(const ViewDesc *views, in
             val = (float)(vd.cx0 +
                           (((double)x0 + 0.5 * (double)w) - 0.5 * (double)vd.n) * vd.dx);
         else if (lane == 1)
-            val = (float)(vd.ytab_off >= 0
-                              ? ytab[vd.ytab_off + y0 + h / 2]
+            val = (float)(vd.rows_off >= 0
+                              ? rows[vd.rows_off + y0 + h / 2].cy
                               : vd.cy0 + (((double)y0 + 0.5 * (double)h) - 0.5 * (double)vd.m) *
                                              vd.dy);
         else if (lane == 2)
@@ -623,12 +623,12 @@ unsigned blocks_for(int64_t n, int threads, int64_t cap = 1 << 30)
 
 } // namespace
 
-hipError_t launch_features(const ViewDesc *views, int32_t nviews, const double *ytab,
+hipError_t launch_features(const ViewDesc *views, int32_t nviews, const RowRef *rows,
                            int64_t ntiles, int32_t tile_w, int32_t tile_h, int32_t probe_cap,
                            float *feat, hipStream_t s)
 {
     hipLaunchKernelGGL(features_kernel, dim3(blocks_for(ntiles, 4)), dim3(256), 0, s, views,
-                       nviews, ytab, ntiles, tile_w, tile_h, probe_cap, feat);
+                       nviews, rows, ntiles, tile_w, tile_h, probe_cap, feat);
     return hipGetLastError();
 }
 

@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstring>
 #include <algorithm>
+#include <new>
 #include <unordered_map>
 #include <vector>
 
@@ -57,15 +58,15 @@ struct mandel_plan {
     int32_t *d_chunk = nullptr;
     int32_t *d_active = nullptr;
     int64_t active_len = 0;
-    // collapsed rows (tuning.collapse_rows): the distinct row coordinates of every
-    // collapsed view, each full row's compressed row, and the in-place copy passes
-    // that expand a collapsed view's image after the render
-    double *d_ytab = nullptr;
-    int32_t *d_rmap = nullptr;
+    // collapsed rows (tuning.collapse_rows): the rendered rows of every collapsed view
+    // (imaginary part, destination row) and the row copies that complete its image
+    // after the render, as (destination, source) pairs
+    RowRef *d_rows = nullptr;
+    int32_t *d_pairs = nullptr;
     struct Expand {
         int32_t view;
-        int64_t rmap_off;
-        int32_t lo, hi;
+        int64_t pairs_off; // first pair (pairs are int32[2])
+        int32_t npairs;
     };
     std::vector<Expand> expands;
     hipStream_t capture = nullptr;
@@ -74,6 +75,10 @@ struct mandel_plan {
 
 
 namespace {
+
+// Rendered rows, and copied rows, of the collapsed views of one plan at most (each
+// table takes 16 or 8 bytes per row on the host and on the device).
+constexpr int64_t MAX_COLLAPSED_ROWS = (int64_t)1 << 28;
 
 int fill_tuning(const mandel_tuning *t, mandel_tuning *o)
 {
@@ -218,7 +223,7 @@ int enqueue(mandel_plan *p, int32_t *out, const mandel_launch &la, hipStream_t s
     if (la.mode == MANDEL_PLAN_ORDERED) {
         order = la.order;
     } else if (la.mode == MANDEL_PLAN_PROBE_LPT || la.mode == MANDEL_PLAN_LEARNED_LPT) {
-        e = launch_features(p->d_views, (int32_t)p->views.size(), p->d_ytab, p->ntiles,
+        e = launch_features(p->d_views, (int32_t)p->views.size(), p->d_rows, p->ntiles,
                             p->tune.tile_w,
                             p->tune.tile_h, la.probe_cap, p->d_feat, s);
         if (e != hipSuccess)
@@ -251,7 +256,7 @@ int enqueue(mandel_plan *p, int32_t *out, const mandel_launch &la, hipStream_t s
     a.parts = p->tune.tile_parts;
     a.first_slot = la.first_slot;
     a.nrows = p->nrows;
-    a.ytab = p->d_ytab;
+    a.rows = p->d_rows;
     a.out = out;
     a.head = rows ? nullptr : p->d_head;
     a.order = order;
@@ -280,7 +285,7 @@ int enqueue(mandel_plan *p, int32_t *out, const mandel_launch &la, hipStream_t s
         return hip_fail(e, "render launch");
     for (const mandel_plan::Expand &x : p->expands) {
         const ViewDesc &v = p->views[(size_t)x.view];
-        e = launch_expand_rows(out + v.out_off, v.n, p->d_rmap + x.rmap_off, x.lo, x.hi, s);
+        e = launch_expand_rows(out + v.out_off, v.n, p->d_pairs + 2 * x.pairs_off, x.npairs, s);
         if (e != hipSuccess)
             return hip_fail(e, "row expansion launch");
     }
@@ -294,17 +299,17 @@ int enqueue(mandel_plan *p, int32_t *out, const mandel_launch &la, hipStream_t s
 // too, bit for bit (rounding to nearest is symmetric in sign, so the orbit of the
 // conjugate is the conjugate orbit), so with mirror set rows whose imaginary parts
 // differ only in sign are merged as well.  Such a view is rendered as m' <= m rows, one
-// per distinct key in order of first occurrence (the first row's cy kept in ytab),
-// into the first m' rows of its image, and afterwards copied out: row i takes
-// rendered row rmap[i] <= i.  The copies run in passes over ranges [lo, hi) whose
-// sources all lie below lo, from the bottom of the image up; a row is overwritten only
-// after every row that copies it has been written, so the copies run in place.
-int collapse_rows(mandel_plan *p, int32_t k, bool mirror, std::vector<double> &ytab,
-                  std::vector<int32_t> &rmap)
+// per distinct key in order of first occurrence, each written straight into the image
+// row where its key first occurs; afterwards every other row copies the row where its
+// key first occurs.  Those source rows are never copy destinations, so all copies of
+// a view run in one launch, in any order.
+int collapse_rows(mandel_plan *p, int32_t k, bool mirror, std::vector<RowRef> &rows,
+                  std::vector<int32_t> &pairs)
 {
     ViewDesc &d = p->views[(size_t)k];
     const int32_t m = d.m;
-    std::vector<double> ys;
+    std::vector<double> ys;     // imaginary part of each distinct key, in first-occurrence order
+    std::vector<int32_t> first; // the image row where each key first occurs
     std::vector<int32_t> map((size_t)m);
     std::unordered_map<uint64_t, int32_t> seen;
     for (int32_t i = 0; i < m; ++i) {
@@ -318,37 +323,31 @@ int collapse_rows(mandel_plan *p, int32_t k, bool mirror, std::vector<double> &y
         if (it == seen.end()) {
             it = seen.emplace(bits, (int32_t)ys.size()).first;
             ys.push_back(cy);
+            first.push_back(i);
         }
         map[(size_t)i] = it->second;
     }
-    if ((int32_t)ys.size() == m)
+    const int64_t copies = m - (int64_t)ys.size();
+    if (copies == 0)
         return MANDEL_OK; // every row distinct
-    if ((int64_t)ytab.size() + (int64_t)ys.size() > INT32_MAX ||
-        (int64_t)rmap.size() + m > ((int64_t)1 << 40))
-        return fail(MANDEL_EINVAL, "view %d: too many collapsed rows in one plan", k);
-    d.ytab_off = (int32_t)ytab.size();
-    ytab.insert(ytab.end(), ys.begin(), ys.end());
-    const int64_t rmap_off = (int64_t)rmap.size();
-    rmap.insert(rmap.end(), map.begin(), map.end());
+    if ((int64_t)rows.size() + (int64_t)ys.size() > MAX_COLLAPSED_ROWS ||
+        (int64_t)pairs.size() / 2 + copies > MAX_COLLAPSED_ROWS)
+        return fail(MANDEL_EINVAL, "view %d: more than 2^28 rendered or copied rows in the "
+                    "collapsed views of one plan", k);
+    d.rows_off = (int32_t)rows.size();
+    for (size_t r = 0; r < ys.size(); ++r)
+        rows.push_back({ys[r], d.out_off + (int64_t)first[r] * d.n});
+    const int64_t pairs_off = (int64_t)pairs.size() / 2;
+    for (int32_t i = 0; i < m; ++i) {
+        const int32_t src = first[(size_t)map[(size_t)i]];
+        if (src != i) {
+            pairs.push_back(i);
+            pairs.push_back(src);
+        }
+    }
     d.m = (int32_t)ys.size();
     d.tiles_y = (int32_t)(((int64_t)d.m + p->tune.tile_h - 1) / p->tune.tile_h);
-    // Passes, top down.  A row with map[i] == i holds its own rendered row and stays.
-    // Otherwise the pass takes rows downward from hi - 1 while every source of the
-    // pass stays below its lowest row (map[i] <= i, so row hi - 1 alone qualifies).
-    for (int32_t hi = m; hi > 0;) {
-        if (map[(size_t)hi - 1] == hi - 1) {
-            --hi;
-            continue;
-        }
-        int32_t lo = hi - 1, top = map[(size_t)hi - 1];
-        while (lo > 0 && map[(size_t)lo - 1] != lo - 1 &&
-               std::max(top, map[(size_t)lo - 1]) < lo - 1) {
-            top = std::max(top, map[(size_t)lo - 1]);
-            --lo;
-        }
-        p->expands.push_back({k, rmap_off, lo, hi});
-        hi = lo;
-    }
+    p->expands.push_back({k, pairs_off, (int32_t)copies});
     return MANDEL_OK;
 }
 
@@ -373,35 +372,40 @@ int mandel_plan_create(const mandel_view *views, int32_t nviews, const mandel_tu
     if (!p)
         return fail(MANDEL_ENOMEM, "host allocation failed");
     p->tune = tu;
-    p->views.resize((size_t)nviews);
     int64_t toff = 0, npx = 0;
-    std::vector<double> ytab;
-    std::vector<int32_t> rmap;
-    for (int32_t k = 0; k < nviews; ++k) {
-        const mandel_view &v = views[k];
-        rc = make_view(&v.w, v.m, v.n, v.max_iter, v.R, tu.tile_w, tu.tile_h, &p->views[k]);
-        if (rc) {
-            delete p;
-            return fail(rc, "view %d: %s", k, mandel_last_error());
-        }
-        if (v.out_offset < 0) {
-            delete p;
-            return fail(MANDEL_EINVAL, "view %d: negative out_offset", k);
-        }
-        ViewDesc &d = p->views[k];
-        d.out_off = v.out_offset;
-        if (tu.collapse_rows && v.m > 1 && v.n > 0) {
-            rc = collapse_rows(p, k, tu.collapse_rows == 2, ytab, rmap);
+    std::vector<RowRef> rows;
+    std::vector<int32_t> pairs;
+    try { // the host tables of a large plan may not fit
+        p->views.resize((size_t)nviews);
+        for (int32_t k = 0; k < nviews; ++k) {
+            const mandel_view &v = views[k];
+            rc = make_view(&v.w, v.m, v.n, v.max_iter, v.R, tu.tile_w, tu.tile_h, &p->views[k]);
             if (rc) {
                 delete p;
-                return rc;
+                return fail(rc, "view %d: %s", k, mandel_last_error());
             }
+            if (v.out_offset < 0) {
+                delete p;
+                return fail(MANDEL_EINVAL, "view %d: negative out_offset", k);
+            }
+            ViewDesc &d = p->views[k];
+            d.out_off = v.out_offset;
+            if (tu.collapse_rows && v.m > 1 && v.n > 0) {
+                rc = collapse_rows(p, k, tu.collapse_rows == 2, rows, pairs);
+                if (rc) {
+                    delete p;
+                    return rc;
+                }
+            }
+            d.tile_off = toff;
+            d.row_off = p->nrows;
+            toff += tile_count(d.m, d.n, tu.tile_w, tu.tile_h);
+            p->nrows += d.m;
+            npx += (int64_t)v.m * v.n;
         }
-        d.tile_off = toff;
-        d.row_off = p->nrows;
-        toff += tile_count(d.m, d.n, tu.tile_w, tu.tile_h);
-        p->nrows += d.m;
-        npx += (int64_t)v.m * v.n;
+    } catch (const std::bad_alloc &) {
+        delete p;
+        return fail(MANDEL_ENOMEM, "host allocation failed");
     }
     if (toff >= ((int64_t)1 << 31)) {
         delete p;
@@ -417,15 +421,15 @@ int mandel_plan_create(const mandel_view *views, int32_t nviews, const mandel_tu
                       hipMemcpyHostToDevice);
     if (e == hipSuccess)
         e = hipMalloc((void **)&p->d_head, HEAD_BYTES);
-    if (e == hipSuccess && !ytab.empty()) {
-        e = hipMalloc((void **)&p->d_ytab, sizeof(double) * ytab.size());
+    if (e == hipSuccess && !rows.empty()) {
+        e = hipMalloc((void **)&p->d_rows, sizeof(RowRef) * rows.size());
         if (e == hipSuccess)
-            e = hipMemcpy(p->d_ytab, ytab.data(), sizeof(double) * ytab.size(),
+            e = hipMemcpy(p->d_rows, rows.data(), sizeof(RowRef) * rows.size(),
                           hipMemcpyHostToDevice);
         if (e == hipSuccess)
-            e = hipMalloc((void **)&p->d_rmap, sizeof(int32_t) * rmap.size());
+            e = hipMalloc((void **)&p->d_pairs, sizeof(int32_t) * pairs.size());
         if (e == hipSuccess)
-            e = hipMemcpy(p->d_rmap, rmap.data(), sizeof(int32_t) * rmap.size(),
+            e = hipMemcpy(p->d_pairs, pairs.data(), sizeof(int32_t) * pairs.size(),
                           hipMemcpyHostToDevice);
     }
     if (e == hipSuccess)
@@ -582,7 +586,7 @@ int mandel_plan_features(mandel_plan *p, float *feat, int32_t probe_cap, void *s
         return MANDEL_OK;
     if (!feat)
         return fail(MANDEL_EINVAL, "feat is NULL");
-    hipError_t e = launch_features(p->d_views, (int32_t)p->views.size(), p->d_ytab, p->ntiles,
+    hipError_t e = launch_features(p->d_views, (int32_t)p->views.size(), p->d_rows, p->ntiles,
                                    p->tune.tile_w, p->tune.tile_h, probe_cap, feat,
                                    (hipStream_t)stream);
     return e == hipSuccess ? MANDEL_OK : hip_fail(e, "features launch");
@@ -610,8 +614,8 @@ int mandel_plan_destroy(mandel_plan *p)
     (void)hipFree(p->d_hist);
     (void)hipFree(p->d_chunk);
     (void)hipFree(p->d_active);
-    (void)hipFree(p->d_ytab);
-    (void)hipFree(p->d_rmap);
+    (void)hipFree(p->d_rows);
+    (void)hipFree(p->d_pairs);
     delete p;
     return MANDEL_OK;
 }

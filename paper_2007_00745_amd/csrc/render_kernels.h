@@ -16,6 +16,13 @@ enum : int {
 // Bytes of a queue head allocation (one 64-bit counter on its own 256-byte line).
 constexpr int HEAD_BYTES = 256;
 
+// One rendered row of a view with collapsed rows: its imaginary part and the element
+// offset, in the output buffer, of the image row that receives its counts.
+struct RowRef {
+    double cy;
+    int64_t out;
+};
+
 // One view as the kernels see it (96 bytes).
 struct ViewDesc {
     double cx0, cy0, dx, dy; // window: centre and pixel pitch
@@ -27,9 +34,10 @@ struct ViewDesc {
     int32_t max_iter;
     int32_t tiles_x;         // tiles per tile-row
     int32_t tiles_y;
-    int32_t ytab_off;        // -1: row i has cy = cy0 + ((i + 0.5) - m/2) dy; >= 0: the
-                             // view's rows are the distinct row coordinates of a larger
-                             // view (collapsed rows), row i's cy = ytab[ytab_off + i]
+    int32_t rows_off;        // -1: row i has cy = cy0 + ((i + 0.5) - m/2) dy and its
+                             // counts go to image row i; >= 0: the view's rows are the
+                             // distinct row coordinates of a larger view (collapsed
+                             // rows), row i is rows[rows_off + i]
     int64_t row_off;         // batch row policies: index of this view's first row in the
                              // concatenation of all views' rows
 };
@@ -47,7 +55,7 @@ struct RenderArgs {
     int32_t parts;                 // queue items per tile (row parts), >= 1; 1 for GRID
     int64_t first_slot;            // FCFS / ORDERED: the queue starts at this slot
     int64_t nrows;                 // batch row policies: rows of all views together
-    const double *ytab;            // row coordinates of views with collapsed rows, or NULL
+    const RowRef *rows;            // rows of views with collapsed rows, or NULL
     int32_t *out;                  // output base
     unsigned long long *head;      // queue head (FCFS / ORDERED)
     const int32_t *order;          // ORDERED: queue slot -> tile id
@@ -78,9 +86,10 @@ hipError_t launch_clear(unsigned long long *head, int64_t first_slot, int64_t *t
                         hipStream_t s, int32_t *chunk = nullptr, int32_t *active = nullptr,
                         int64_t nwaves = 0);
 int persistent_blocks_per_cu(int policy, bool batch, int tests, int threads);
-// Copies whole rows inside one view's image: row i of [lo, hi) becomes a copy of row
-// rmap[i] (rmap[i] < lo for every such i), n columns per row.
-hipError_t launch_expand_rows(int32_t *img, int64_t n, const int32_t *rmap, int32_t lo, int32_t hi,
+// Copies whole rows inside one view's image: for each of the npairs pairs (dst, src)
+// in pairs[2 * npairs], row dst becomes a copy of row src, n columns per row.  No src
+// may be a dst of the same call (the copies run in any order).
+hipError_t launch_expand_rows(int32_t *img, int64_t n, const int32_t *pairs, int32_t npairs,
                               hipStream_t s);
 
 } // namespace mandel

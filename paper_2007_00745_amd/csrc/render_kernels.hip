@@ -122,7 +122,7 @@ __device__ __forceinline__ ViewDesc load_view(const __attribute__((address_space
     d.max_iter = p->max_iter;
     d.tiles_x = p->tiles_x;
     d.tiles_y = p->tiles_y;
-    d.ytab_off = p->ytab_off;
+    d.rows_off = p->rows_off;
     d.row_off = p->row_off;
     return d;
 }
@@ -577,12 +577,15 @@ render_kernel(RenderArgs a)
                 const double offx = ((double)j + 0.5) - 0.5 * (double)vd->n;
                 const double px = offx * vd->dx;
                 cx = vd->cx0 + px;
-                if (BATCH && vd->ytab_off >= 0) {
-                    cy = a.ytab[vd->ytab_off + i];
+                if (BATCH && vd->rows_off >= 0) {
+                    const RowRef rr = a.rows[vd->rows_off + i];
+                    cy = rr.cy;
+                    oidx = rr.out + j;
                 } else {
                     const double offy = ((double)i + 0.5) - 0.5 * (double)vd->m;
                     const double py = offy * vd->dy;
                     cy = vd->cy0 + py;
+                    oidx = vd->out_off + (int64_t)i * vd->n + j;
                 }
                 x = 0.0;
                 y = 0.0;
@@ -590,7 +593,6 @@ render_kernel(RenderArgs a)
                     R2 = vd->R2;
                 start = W;
                 deadline = W + (uint32_t)(vd->max_iter - 1);
-                oidx = vd->out_off + (int64_t)i * vd->n + j;
                 ltile = s_tile;
                 if constexpr (DEFER) {
                     const double cc = cx * cx + cy * cy;
@@ -657,17 +659,28 @@ render_kernel(RenderArgs a)
         return m;
     };
 
+    // A lower bound of deadline - W over the active lanes, carried from one round to the
+    // next: W and the bound advance together, a replay only moves a deadline later and a
+    // finished lane leaves the set, so only a refill invalidates it.  While it allows a
+    // whole block the exact minimum (a cross-lane reduction) is not needed.
+    uint32_t bound = 0;
+
     // Invariant at the top of each round: every active lane holds the state
     // z_n, n = W - start, not yet tested, and W <= deadline.
     for (;;) {
         const uint64_t idle = ballot(!active);
-        if ((uint32_t)__popcll(idle) >= Rs) // also when no lane is active (Rs <= 8)
+        if ((uint32_t)__popcll(idle) >= Rs) { // also when no lane is active (Rs <= 8)
             refill();
+            bound = 0;
+        }
         const uint64_t amask = ballot(active);
         if (amask == 0)
             break;
-        // updates until the first lane reaches its last state z_{max_iter-1}
-        uint32_t budget = wave_min_u32(active ? deadline - W : 0xffffffffu);
+        // updates until the first lane reaches its last state z_{max_iter-1} (or a lower
+        // bound of that, when it still allows a full block: finalisation at a deadline is
+        // decided per lane, so a low bound only ends a round early)
+        uint32_t budget =
+            bound >= Kc ? bound : wave_min_u32(active ? deadline - W : 0xffffffffu);
 
         if constexpr (DEFER) {
             const bool needc = active && (pending || !safe || (W - start) < P);
@@ -774,6 +787,7 @@ render_kernel(RenderArgs a)
                 }
                 // lanes now at z_{max_iter-1} with no escape so far: count = max_iter
                 finalize(active && !pending && deadline == W, false);
+                bound = budget;
                 continue;
             }
         }
@@ -838,6 +852,7 @@ render_kernel(RenderArgs a)
                         continue;
                     }
                 }
+                budget = budget >= 4 ? budget - 4 : 0; // this group's updates
                 break;
             }
             budget -= 4;
@@ -845,6 +860,7 @@ render_kernel(RenderArgs a)
             if (DEFER && done >= climit)
                 break; // re-evaluate the mode
         }
+        bound = budget;
     }
 
     if (a.stats) {
@@ -942,41 +958,39 @@ hipError_t launch_render(const RenderArgs &a, int policy, bool batch, int tests,
     }
 }
 
-// Rows [lo, hi) of an image of n columns become copies of rows rmap[i] < lo; 16-byte
-// vectors when the rows are 16-byte aligned.
-__global__ void expand_rows_kernel(int32_t *img, int64_t n, const int32_t *rmap, int32_t lo,
-                                   int32_t hi)
+// Pair p0 + blockIdx.y (dst, src) of an image of n columns: row dst becomes a copy of
+// row src, in 16-byte vectors when the rows are 16-byte aligned.
+__global__ void expand_rows_kernel(int32_t *img, int64_t n, const int32_t *pairs, int32_t p0,
+                                   int32_t npairs)
 {
-    const int32_t i = lo + (int32_t)blockIdx.y;
-    if (i >= hi)
+    const int32_t q = p0 + (int32_t)blockIdx.y;
+    if (q >= npairs)
         return;
-    const int32_t src = rmap[i];
-    int32_t *dst = img + (int64_t)i * n;
-    const int32_t *from = img + (int64_t)src * n;
+    int32_t *dst = img + (int64_t)pairs[2 * q] * n;
+    const int32_t *from = img + (int64_t)pairs[2 * q + 1] * n;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     if ((n & 3) == 0 && (((uintptr_t)img) & 15) == 0) {
         const int64_t n4 = n >> 2;
-        for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n4; q += stride)
-            ((int4 *)dst)[q] = ((const int4 *)from)[q];
+        for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n4; c += stride)
+            ((int4 *)dst)[c] = ((const int4 *)from)[c];
     } else {
-        for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += stride)
-            dst[q] = from[q];
+        for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += stride)
+            dst[c] = from[c];
     }
 }
 
-hipError_t launch_expand_rows(int32_t *img, int64_t n, const int32_t *rmap, int32_t lo, int32_t hi,
+hipError_t launch_expand_rows(int32_t *img, int64_t n, const int32_t *pairs, int32_t npairs,
                               hipStream_t s)
 {
-    if (hi <= lo || n <= 0)
+    if (npairs <= 0 || n <= 0)
         return hipSuccess;
     const int64_t per_row = (n + 4 * 256 - 1) / (4 * 256);
     const unsigned gx = (unsigned)(per_row < 64 ? per_row : 64);
-    const unsigned rows = (unsigned)(hi - lo);
     // grid.y is limited to 65535 rows per launch
-    for (unsigned r0 = 0; r0 < rows; r0 += 65535u) {
-        const unsigned nr = rows - r0 < 65535u ? rows - r0 : 65535u;
-        hipLaunchKernelGGL(expand_rows_kernel, dim3(gx, nr), dim3(256), 0, s, img, n, rmap,
-                           lo + (int32_t)r0, lo + (int32_t)(r0 + nr));
+    for (int32_t p0 = 0; p0 < npairs; p0 += 65535) {
+        const unsigned nr = npairs - p0 < 65535 ? (unsigned)(npairs - p0) : 65535u;
+        hipLaunchKernelGGL(expand_rows_kernel, dim3(gx, nr), dim3(256), 0, s, img, n, pairs, p0,
+                           npairs);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess)
             return e;

@@ -492,7 +492,9 @@ def _collapsing_views():
     # row coordinate; view 1 likewise with ragged sizes against 64x8 tiles; view 2 an
     # ordinary zoom (nothing to collapse); view 3 empty; view 4 a single row
     # (ordinary for rows that merge by value); views 5 and 6 are centred on the real
-    # axis (even and odd row counts), so their rows pair up by conjugation
+    # axis (even and odd row counts), so their rows pair up by conjugation; view 7 has a
+    # pitch just below the spacing of doubles, so only a few scattered rows repeat the
+    # row before them and most rows are copied from a row of another index
     cx, cy = workloads.boundary_centre(745, 0)
     return [workloads.View((cx, cy, 2e-15, 1e-17), 157, 96, 2000),
             workloads.View((cx, cy + 3e-15, 3e-15, 2.5e-17), 61, 70, 900),
@@ -501,7 +503,8 @@ def _collapsing_views():
             workloads.View((cx, cy, 1e-15, 1e-17), 1, 33, 400),
             workloads.View(workloads.window_from_bounds(-2.0, 1.0, -1.2, 1.2, 96, 120), 96,
                            120, 600),
-            workloads.View((-0.75, 0.0, 1e-3, 1e-3), 37, 81, 1500)]
+            workloads.View((-0.75, 0.0, 1e-3, 1e-3), 37, 81, 1500),
+            workloads.View((cx, cy, 1e-14, 0.97 * float(np.spacing(cy))), 200, 40, 800)]
 
 
 def _distinct_rows(v, mirror=False):
@@ -529,6 +532,7 @@ def test_collapsed_rows_match_the_oracle(mode, use_graph, collapse):
     mirror = collapse == 2
     distinct = [int(_distinct_rows(v, mirror)[1].sum()) for v in views]
     assert distinct[0] < views[0].m // 5 and distinct[2] == views[2].m
+    assert views[7].m - 10 < distinct[7] < views[7].m
     if mirror:
         assert distinct[5] == 48 and distinct[6] == 19
     assert plan.ntiles < flat.ntiles
