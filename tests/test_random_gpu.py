@@ -3,13 +3,14 @@ same cases): each case draws a small batch of views (full window, boundary zooms
 down to pitch 1e-9, random regions, the all-escaping outside; ragged and empty
 sizes; max_iter 1..3000; R from 1.5 to 400), a random plan tuning (tile shape,
 claim grain, wavefronts per group, deferred block length, young updates, refill
-lanes, row parts, group count) and two random launches of the same plan (FCFS,
-ordered over a random permutation, probe, learned with random weights, the
+lanes, row parts, group count, collapsed rows, the latter with a zoom whose row
+pitch lies below the spacing of doubles) and two random launches of the same plan
+(FCFS, ordered over a random permutation, probe, learned with random weights, the
 paper's static and alternating rows over the concatenated rows; periodicity
 detection, row stealing, eager or from the graph).  Every image must equal the
 oracle's bit for bit (Sec. I, Eq. (1)-(2): the schedule never changes a count),
-the statistics' count sum must equal the oracle's, and in the queue modes so must
-the per-tile cost log's total."""
+the statistics' count sum must equal the oracle's over the rendered rows, and in the
+queue modes so must the per-tile cost log's total."""
 import sys
 
 import numpy as np
@@ -65,6 +66,23 @@ def _tuning(rng):
                 groups=int(rng.choice([0, 0, 37, 300])))
 
 
+def _rendered_total(views, want, collapse):
+    # the count sum over the rows a plan renders: with collapsed rows, only the first
+    # row of each imaginary part (of each absolute value with collapse 2), formed as the
+    # kernels form it; the other rows are copies
+    total = 0
+    for v, w in zip(views, want):
+        if collapse == 0 or v.m < 2 or v.n == 0:
+            total += int(w.sum(dtype=np.int64))
+            continue
+        i = np.arange(v.m, dtype=np.float64)
+        cy = v.window[1] + ((i + 0.5) - v.m / 2.0) * v.window[3]
+        key = np.abs(cy) if collapse == 2 else cy + 0.0
+        _, first = np.unique(key, return_index=True)
+        total += int(w[first].sum(dtype=np.int64))
+    return total
+
+
 def _launch_kw(rng, plan, params):
     mode = str(rng.choice(["fcfs", "ordered", "probe", "learned", "static", "alternating"]))
     kw = dict(mode=mode, use_graph=bool(rng.random() < 0.5),
@@ -86,9 +104,22 @@ def _launch_kw(rng, plan, params):
 def test_random_batch_and_schedule(seed):
     rng = np.random.default_rng(9000 + seed)
     views = [_view(rng) for _ in range(int(rng.integers(1, 5)))]
+    # collapsed rows from a generator of their own, so the other draws stay as they were;
+    # with them, one more view whose row pitch is 0.05-1.5 times the spacing of doubles
+    # near its imaginary part, so that some or most of its rows share a coordinate
+    crng = np.random.default_rng(31000 + seed)
+    collapse = int(crng.choice([0, 0, 1, 2]))
+    if collapse:
+        cx, cy = NEAR_BOUNDARY[int(crng.choice([0, 1, 2, 5]))]
+        dy = float(np.spacing(cy)) * crng.uniform(0.05, 1.5)
+        views.append(workloads.View((cx, cy, 10.0 ** crng.uniform(-9, -6), dy),
+                                    int(crng.integers(2, 120)), int(crng.integers(1, 90)),
+                                    int(np.exp(crng.uniform(0.0, np.log(3000.0)))), 2.0))
     want = [oracle.render(v.window, v.m, v.n, v.max_iter, v.R) for v in views]
     total = sum(int(w.sum(dtype=np.int64)) for w in want)
     tun = _tuning(rng)
+    tun["collapse_rows"] = collapse
+    rendered = _rendered_total(views, want, collapse)
     plan = native.Plan(views, tun)
     p = mlp_ref.init_params(rng, mu=rng.normal(size=68) * 0.1, sd=rng.uniform(0.5, 2.0, 68))
     params = torch.tensor(p, dtype=torch.float32, device="cuda")
@@ -112,9 +143,9 @@ def test_random_batch_and_schedule(seed):
         for k, (g, w) in enumerate(zip(imgs, want)):
             assert np.array_equal(g.numpy(), w), f"seed {seed} rep {rep} view {k}"
         if plan.ntiles > 0:
-            assert int(stats.cpu()[1]) == total
+            assert int(stats.cpu()[1]) == rendered
             if not rows:
-                assert int(cost[:plan.ntiles].sum().item()) == total
+                assert int(cost[:plan.ntiles].sum().item()) == rendered
     plan.close()
 
 
