@@ -5,17 +5,16 @@
 #include <hip/hip_runtime.h>
 
 #include <climits>
-#include <cmath>
 #include <cstring>
 #include <algorithm>
 #include <new>
-#include <unordered_map>
 #include <vector>
 
 #include "costmodel.h"
 #include "mandel.h"
 #include "mandel_internal.h"
 #include "render_kernels.h"
+#include "row_collapse.h"
 
 using namespace mandel;
 
@@ -292,60 +291,28 @@ int enqueue(mandel_plan *p, int32_t *out, const mandel_launch &la, hipStream_t s
     return MANDEL_OK;
 }
 
-// Collapsed rows.  Row i of view k has imaginary part cy0 + ((i + 0.5) - m/2) dy (one
-// rounded product, one rounded sum, exactly as the kernels form it).  Rows with the
-// same c have the same counts: when dy is below the spacing of doubles near cy0,
-// neighbouring rows round to the same value.  Conjugate points have the same counts
-// too, bit for bit (rounding to nearest is symmetric in sign, so the orbit of the
-// conjugate is the conjugate orbit), so with mirror set rows whose imaginary parts
-// differ only in sign are merged as well.  Such a view is rendered as m' <= m rows, one
-// per distinct key in order of first occurrence, each written straight into the image
-// row where its key first occurs; afterwards every other row copies the row where its
-// key first occurs.  Those source rows are never copy destinations, so all copies of
-// a view run in one launch, in any order.
+// Collapsed rows (planned by plan_row_collapse): view k is rendered as its distinct
+// rows, each written to the image row where its key first occurs, and the copies of
+// the other rows are queued for after the render.
 int collapse_rows(mandel_plan *p, int32_t k, bool mirror, std::vector<RowRef> &rows,
                   std::vector<int32_t> &pairs)
 {
     ViewDesc &d = p->views[(size_t)k];
-    const int32_t m = d.m;
-    std::vector<double> ys;     // imaginary part of each distinct key, in first-occurrence order
-    std::vector<int32_t> first; // the image row where each key first occurs
-    std::vector<int32_t> map((size_t)m);
-    std::unordered_map<uint64_t, int32_t> seen;
-    for (int32_t i = 0; i < m; ++i) {
-        const double off = ((double)i + 0.5) - 0.5 * (double)m;
-        const double py = off * d.dy;
-        const double cy = d.cy0 + py;
-        const double key = mirror ? std::fabs(cy) : cy + 0.0; // + 0.0: -0 and +0 alike
-        uint64_t bits;
-        std::memcpy(&bits, &key, sizeof bits);
-        auto it = seen.find(bits);
-        if (it == seen.end()) {
-            it = seen.emplace(bits, (int32_t)ys.size()).first;
-            ys.push_back(cy);
-            first.push_back(i);
-        }
-        map[(size_t)i] = it->second;
-    }
-    const int64_t copies = m - (int64_t)ys.size();
+    RowCollapse rc;
+    plan_row_collapse(d.cy0, d.dy, d.m, mirror, rc);
+    const int64_t copies = (int64_t)rc.pairs.size() / 2;
     if (copies == 0)
         return MANDEL_OK; // every row distinct
-    if ((int64_t)rows.size() + (int64_t)ys.size() > MAX_COLLAPSED_ROWS ||
+    if ((int64_t)rows.size() + (int64_t)rc.cy.size() > MAX_COLLAPSED_ROWS ||
         (int64_t)pairs.size() / 2 + copies > MAX_COLLAPSED_ROWS)
         return fail(MANDEL_EINVAL, "view %d: more than 2^28 rendered or copied rows in the "
                     "collapsed views of one plan", k);
     d.rows_off = (int32_t)rows.size();
-    for (size_t r = 0; r < ys.size(); ++r)
-        rows.push_back({ys[r], d.out_off + (int64_t)first[r] * d.n});
+    for (size_t r = 0; r < rc.cy.size(); ++r)
+        rows.push_back({rc.cy[r], d.out_off + (int64_t)rc.first[r] * d.n});
     const int64_t pairs_off = (int64_t)pairs.size() / 2;
-    for (int32_t i = 0; i < m; ++i) {
-        const int32_t src = first[(size_t)map[(size_t)i]];
-        if (src != i) {
-            pairs.push_back(i);
-            pairs.push_back(src);
-        }
-    }
-    d.m = (int32_t)ys.size();
+    pairs.insert(pairs.end(), rc.pairs.begin(), rc.pairs.end());
+    d.m = (int32_t)rc.cy.size();
     d.tiles_y = (int32_t)(((int64_t)d.m + p->tune.tile_h - 1) / p->tune.tile_h);
     p->expands.push_back({k, pairs_off, (int32_t)copies});
     return MANDEL_OK;
