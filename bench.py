@@ -624,6 +624,44 @@ def profile_batch(torch, native, workloads, costmodel, steps: int) -> dict:
     return res
 
 
+# Single views of the counter table of the render kernel: what its instruction mix
+# looks like with no escapes, with the headline's mix at a smaller size, with dense
+# escapes, and with every pixel escaping at once.
+PROFILE_VIEWS = {
+    "interior": ((-0.2, 0.0, 0.2 / 2048, 0.2 / 2048), 2048, 2048, 10000),
+    "full_4096": (None, 4096, 4096, 10000),
+    "seahorse": ((-0.745, 0.113, 0.01 / 2048, 0.01 / 2048), 2048, 2048, 10000),
+    "exterior": ((3.0, 3.0, 0.5 / 4096, 0.5 / 4096), 4096, 4096, 10000),
+}
+
+
+def profile_view(torch, native, workloads, name: str, steps: int) -> dict:
+    """Counter runs on one view of PROFILE_VIEWS through a one-view plan (64x8 tiles):
+    one FCFS launch logs the tile costs, then `steps` ordered launches in the true-cost
+    order; returns the figures that turn per-dispatch counters into per-iteration rates."""
+    win, m, n, max_iter = PROFILE_VIEWS[name]
+    v = workloads.c2(m, max_iter) if win is None else workloads.View(win, m, n, max_iter)
+    torch.cuda.set_device(0)
+    plan = native.Plan([v])
+    out = torch.empty(plan.out_size(), dtype=torch.int32, device="cuda")
+    cost = torch.empty(plan.ntiles, dtype=torch.int64, device="cuda")
+    plan.launch(out, tile_cost=cost)
+    torch.cuda.synchronize()
+    perm = native.order_desc(native.cost_targets(cost))
+    stats = torch.zeros(8, dtype=torch.int64, device="cuda")
+    for _ in range(steps):
+        plan.launch(out, mode="ordered", order=perm, stats=stats)
+    torch.cuda.synchronize()
+    st = [int(x) for x in stats.cpu().tolist()]
+    sum_counts = int(cost.sum().item())
+    assert st[1] == steps * sum_counts
+    plan.close()
+    return {"view": name, "window": list(v.window), "m": v.m, "n": v.n,
+            "max_iter": v.max_iter, "sum_counts": sum_counts,
+            "render_wave_iterations_per_launch": st[0] / steps,
+            "lane_occupancy": st[1] / (64.0 * st[0]) if st[0] else None}
+
+
 def stress_batch(torch, native, workloads, costmodel, reps: int, clock_khz: float, params,
                  cus: int, contiguous_rows: bool = False) -> dict:
     """Stress batch in one plan (64x8 tiles, blocks of at most 128 updates): a 16384 x
@@ -859,6 +897,10 @@ def main():
                          "kernel, the cost-model inference kernel (untrained weights) and the "
                          "ordered render in the true-cost order, on the plan the makespan "
                          "comparison uses; prints one JSON line and nothing else runs")
+    ap.add_argument("--profile-view", choices=sorted(PROFILE_VIEWS),
+                    help="run for counters on one single view: one FCFS launch logs the "
+                         "tile costs, then --steps ordered launches in the true-cost order; "
+                         "prints one JSON line and nothing else runs")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -872,6 +914,10 @@ def main():
     native.lib()  # fails loudly when the library is missing
     if args.profile_batch:
         print(json.dumps(profile_batch(torch, native, workloads, costmodel, args.steps)),
+              flush=True)
+        return
+    if args.profile_view:
+        print(json.dumps(profile_view(torch, native, workloads, args.profile_view, args.steps)),
               flush=True)
         return
     view = workloads.c2(args.side, args.max_iter)
