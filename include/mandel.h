@@ -56,10 +56,14 @@ typedef struct mandel_window {
     double dx, dy;   /* pixel pitch: real part per column, imaginary part per row */
 } mandel_window;
 
+/* mandel_sched.tile_parts: choose the row parts per tile from the image size */
+#define MANDEL_TILE_PARTS_AUTO (-1)
+
 /*
  * mandel_render -- the plain entry point: one view, persistent kernel, tiles of
  * 64 x 8 pixels claimed first-come-first-served from a device queue (the
- * device analogue of Sec. III-B).
+ * device analogue of Sec. III-B), in row parts chosen as MANDEL_TILE_PARTS_AUTO
+ * does.
  *   w        host, the window (see above)
  *   m, n     rows and columns; m == 0 or n == 0 is an empty image (no work,
  *            out may be NULL); negative sizes or m*n >= 2^40 are EINVAL
@@ -192,7 +196,12 @@ typedef struct mandel_sched {
     int32_t tile_parts;      /* FCFS / ORDERED: each tile is queued as this many row
                                 parts (rows [p*h/parts, (p+1)*h/parts) of an h-row
                                 tile), so one expensive tile can be shared by several
-                                wavefronts; 1..64 [1]; GRID ignores it */
+                                wavefronts; 1..64, or MANDEL_TILE_PARTS_AUTO: with r
+                                the fewest parts that give at least 24 queue items
+                                per resident wavefront, the largest power of two not
+                                above r, capped at 8 and at tile_h (an image of few
+                                tiles is then not left to a few wavefronts;
+                                first_slot must be 0) [1]; GRID ignores it */
     int32_t periodicity;     /* 1: exact periodicity detection (needs check_every 0):
                                 in each deferred block the last 32 states of every
                                 lane are compared bit for bit with the block-start

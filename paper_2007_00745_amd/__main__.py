@@ -98,6 +98,8 @@ def main(argv=None) -> int:
               "block_iters": args.block_iters or (128 if args.periodicity else 1024)}
         if args.schedule != "fcfs":
             kw["workers"] = args.workers
+        else:
+            kw["tile_parts"] = native.TILE_PARTS_AUTO  # as mandel_render does
         native.render_sched((cx, cy, dx, dy), m, n, args.max_iter, args.radius, out=out, **kw)
     b.record()
     rgb = native.colour_boolean(out, args.max_iter)

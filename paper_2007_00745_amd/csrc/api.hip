@@ -241,10 +241,13 @@ int check_sched(const mandel_sched *s, mandel_sched *o)
         return fail(MANDEL_EINVAL, "refill_lanes=%d outside [1, 64]", d.refill_lanes);
     if (d.tile_parts == 0)
         d.tile_parts = 1;
-    if (d.tile_parts < 1 || d.tile_parts > 64)
-        return fail(MANDEL_EINVAL, "tile_parts=%d outside [1, 64]", d.tile_parts);
-    if (d.policy == MANDEL_GRID_TILES)
+    if (d.tile_parts != MANDEL_TILE_PARTS_AUTO && (d.tile_parts < 1 || d.tile_parts > 64))
+        return fail(MANDEL_EINVAL, "tile_parts=%d outside [1, 64] and not automatic",
+                    d.tile_parts);
+    if (d.policy != MANDEL_FCFS_TILES && d.policy != MANDEL_ORDERED_TILES)
         d.tile_parts = 1;
+    if (d.tile_parts == MANDEL_TILE_PARTS_AUTO && d.first_slot != 0)
+        return fail(MANDEL_EINVAL, "first_slot needs an explicit tile_parts");
     if (d.first_slot < 0)
         return fail(MANDEL_EINVAL, "negative first_slot");
     if (d.first_slot != 0 && d.policy != MANDEL_FCFS_TILES && d.policy != MANDEL_ORDERED_TILES)
@@ -264,6 +267,25 @@ int test_mode(const mandel_sched &s)
 }
 
 // Launch geometry for a tile policy: persistent groups or one group per tile.
+// MANDEL_TILE_PARTS_AUTO: r = the fewest row parts per tile that give at least
+// AUTO_ITEMS_PER_WAVE queue items per resident wavefront; the parts are the largest power
+// of two not above r (parts of equal height in a tile of 8 rows), at most 8 and at most
+// the tile's rows.  Measured on single views with 64 x 8 tiles (FCFS) over 7168
+// wavefronts: 2048^2 views (8192 tiles) took 4.4-4.7 ms in one part and 2.4-2.5 ms in 8;
+// the 4096^2 full view 9.1-9.2 ms in one part, 7.5-7.6 in 4, 7.9 in 6 and 7.8-7.9 in 8;
+// the 8192^2 one 26.5-26.7 ms in one part, 25.5-25.9 in 2 and 30.4-30.6 in 8, where a
+// million claims queue on the head.
+constexpr int64_t AUTO_ITEMS_PER_WAVE = 24;
+
+int32_t auto_tile_parts(int64_t ntiles, int64_t waves, int32_t tile_h)
+{
+    const int64_t r = ntiles > 0 ? (AUTO_ITEMS_PER_WAVE * waves + ntiles - 1) / ntiles : 1;
+    int64_t parts = 1;
+    while (parts * 2 <= r && parts < 8)
+        parts *= 2;
+    return (int32_t)(parts < tile_h ? parts : tile_h);
+}
+
 int tile_grid(const mandel_sched &s, bool batch, int64_t ntiles, dim3 *grid, dim3 *block)
 {
     if (s.policy == MANDEL_GRID_TILES) {
@@ -386,6 +408,9 @@ static int render_sched(const mandel_window *w, int32_t m, int32_t n, int32_t ma
         rc = tile_grid(s, false, ntiles, &grid, &block);
         if (rc)
             return rc;
+        if (s.tile_parts == MANDEL_TILE_PARTS_AUTO)
+            a.parts = auto_tile_parts(ntiles, (int64_t)grid.x * grid.y * (block.x / 64),
+                                      s.tile_h);
     }
     hipError_t e = launch_clear(head, s.first_slot, a.tile_cost, a.claims, a.tile_time,
                                 a.tile_cost || a.claims || a.tile_time ? ntiles : 0, a.stats,
@@ -413,7 +438,11 @@ int mandel_render_sched_noalloc(const mandel_window *w, int32_t m, int32_t n, in
 int mandel_render(const mandel_window *w, int32_t m, int32_t n, int32_t max_iter, double R,
                   int32_t *out, void *stream)
 {
-    return mandel_render_sched(w, m, n, max_iter, R, out, nullptr, stream);
+    mandel_sched s;
+    std::memset(&s, 0, sizeof s);
+    s.policy = MANDEL_FCFS_TILES;
+    s.tile_parts = MANDEL_TILE_PARTS_AUTO;
+    return mandel_render_sched(w, m, n, max_iter, R, out, &s, stream);
 }
 
 int mandel_colour_boolean(const int32_t *counts, int64_t npix, int32_t max_iter, uint8_t *rgb,

@@ -85,6 +85,8 @@ int fill_tuning(const mandel_tuning *t, mandel_tuning *o)
     std::memset(&d, 0, sizeof d);
     if (t)
         d = *t;
+    if (d.tile_parts == MANDEL_TILE_PARTS_AUTO)
+        return fail(MANDEL_EINVAL, "a plan takes an explicit tile_parts (or the autotuner's)");
     mandel_sched s;
     std::memset(&s, 0, sizeof s);
     s.policy = MANDEL_FCFS_TILES;

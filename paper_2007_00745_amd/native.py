@@ -19,6 +19,7 @@ HEADER = os.path.join(os.path.dirname(PKG), "include", "mandel.h")
 OK, EINVAL, ENOMEM, EHIP, EIO = 0, -1, -2, -3, -4
 
 FCFS_TILES, STATIC_ROWS, ALTERNATING_ROWS, ORDERED_TILES, GRID_TILES = 0, 1, 2, 3, 4
+TILE_PARTS_AUTO = -1  # mandel_sched.tile_parts: row parts chosen from the image size
 POLICIES = {
     "fcfs": FCFS_TILES, "static": STATIC_ROWS, "alternating": ALTERNATING_ROWS,
     "ordered": ORDERED_TILES, "grid": GRID_TILES,

@@ -64,5 +64,21 @@ def test_header_has_no_fields_missing_from_binding(tmp_path):
         assert size - end < align, (cname, size, end)
 
 
+def test_binding_constants_match_header(tmp_path):
+    # the policy numbers and the automatic row-parts value as the header defines them
+    src = tmp_path / "consts.c"
+    src.write_text('#include <stdio.h>\n#include "mandel.h"\nint main(void) {\n'
+                   'printf("%d %d %d %d %d %d\\n", MANDEL_FCFS_TILES, MANDEL_STATIC_ROWS, '
+                   'MANDEL_ALTERNATING_ROWS, MANDEL_ORDERED_TILES, MANDEL_GRID_TILES, '
+                   'MANDEL_TILE_PARTS_AUTO);\nreturn 0;\n}\n')
+    exe = tmp_path / "consts"
+    subprocess.run(["gcc", "-std=c11", "-Wall", "-Werror", "-I", os.path.join(ROOT, "include"),
+                    str(src), "-o", str(exe)], check=True, capture_output=True, text=True)
+    got = [int(x) for x in subprocess.run([str(exe)], check=True, capture_output=True,
+                                          text=True).stdout.split()]
+    assert got == [native.FCFS_TILES, native.STATIC_ROWS, native.ALTERNATING_ROWS,
+                   native.ORDERED_TILES, native.GRID_TILES, native.TILE_PARTS_AUTO]
+
+
 if __name__ == "__main__":
     pytest.main([__file__, "-q"])

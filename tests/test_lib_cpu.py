@@ -83,7 +83,7 @@ def test_empty_image_is_a_no_op():
     dict(policy=7), dict(policy=1), dict(policy=3), dict(tile_w=-1), dict(grain=-3),
     dict(waves_per_group=17), dict(check_every=2), dict(block_iters=70000), dict(young_iters=-1),
     dict(workers=-1), dict(refill_lanes=65), dict(refill_lanes=-2), dict(tile_parts=65),
-    dict(tile_parts=-1), dict(first_slot=-1), dict(policy="static", workers=3, first_slot=2),
+    dict(tile_parts=-2), dict(tile_parts=-1, first_slot=3), dict(first_slot=-1), dict(policy="static", workers=3, first_slot=2),
     dict(policy="grid", first_slot=1), dict(periodicity=2), dict(periodicity=1, check_every=1),
 ])
 def test_invalid_schedules(s):
@@ -165,6 +165,16 @@ def test_empty_image_needs_no_order():
     assert _call(m=0, out=None, sched=sched) == native.OK
     assert _call(n=0, out=None, sched=sched) == native.OK
     assert _call(sched=sched) == native.EINVAL   # a real image still needs its order
+
+
+def test_plan_rejects_automatic_row_parts():
+    # plans take an explicit tile_parts (their launches are tuned by the autotuner)
+    v = native.ViewC(native.Window(-0.5, 0.0, 0.01, 0.01), 8, 8, 10, 0, 2.0, 0)
+    arr = (native.ViewC * 1)(v)
+    t = native.Tuning(tile_parts=native.TILE_PARTS_AUTO)
+    h = ctypes.c_void_p()
+    assert native.lib().mandel_plan_create(arr, 1, ctypes.byref(t), ctypes.byref(h)) == native.EINVAL
+    assert b"tile_parts" in native.lib().mandel_last_error()
 
 
 def test_plan_rejects_bad_collapse_flag():

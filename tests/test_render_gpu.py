@@ -117,6 +117,49 @@ def test_claims_and_costs(c1_ref):
         assert st[0] * 64 >= st[1]  # lane iterations cannot exceed lane slots
 
 
+@pytest.mark.parametrize("m,n,tw,th,policy", [
+    (480, 640, 64, 8, "fcfs"), (37, 53, 64, 8, "fcfs"), (1, 97, 64, 8, "fcfs"),
+    (1024, 1024, 64, 8, "fcfs"), (1024, 1024, 64, 3, "ordered"), (300, 2000, 16, 16, "fcfs"),
+    (4096, 4096, 64, 8, "fcfs")])
+def test_automatic_row_parts(m, n, tw, th, policy):
+    # MANDEL_TILE_PARTS_AUTO: one part count p for the launch, 1 <= p <= min(8, tile_h)
+    # (a power of two unless capped by tile_h); every non-empty part of every tile claimed
+    # once; counts equal to the oracle's.  With at least 7168 resident wavefronts (the
+    # MI355X's at 7 per SIMD) an image of at most 24 * 7168 / 8 = 21504 tiles gets the cap.
+    win = workloads.window_from_bounds(-2.0, 1.0, -1.2, 1.2, m, n)
+    v = workloads.View(win, m, n, 600, 2.0)
+    nt = native.tile_count(m, n, tw, th)
+    claims = torch.zeros(nt, dtype=torch.int32, device="cuda")
+    kw = dict(policy=policy, tile_w=tw, tile_h=th, tile_parts=native.TILE_PARTS_AUTO,
+              claims=claims)
+    if policy == "ordered":
+        kw["order"] = torch.randperm(nt, device="cuda").to(torch.int32)
+    got = gpu_render(v, **kw)
+    want = oracle.render(v.window, m, n, v.max_iter, v.R) if m * n <= 1 << 21 else None
+    if want is not None:
+        assert np.array_equal(got, want)
+    else:
+        idx = np.random.default_rng(m + n).integers(0, m * n, 4000)
+        assert np.array_equal(got.ravel()[idx],
+                              oracle.render_pixels(v.window, m, n, v.max_iter, v.R, idx,
+                                                   threads=8))
+        assert np.array_equal(got, got[::-1])  # conjugation symmetry of the whole image
+    c = claims.cpu().numpy().reshape(-(-m // th), -(-n // tw))
+    cap = min(8, th)
+    p = int(c[0, 0]) if m >= th else None
+    if p is not None:
+        assert 1 <= p <= cap and np.all(c[: m // th] == p)
+        rows = m - (m // th) * th  # a ragged last tile row: min(p, rows) non-empty parts
+        if rows:
+            assert np.all(c[-1] == sum(1 for q in range(p) if ((q + 1) * rows) // p > (q * rows) // p))
+        assert p == cap or p in (1, 2, 4), p
+        if nt * 8 <= 24 * 7168:
+            assert p == cap, (nt, p)
+    else:
+        assert np.all((c >= 1) & (c <= cap))
+    _log(f"automatic parts: {nt} tiles -> {p}")
+
+
 @pytest.mark.parametrize("m,n", [(1, 1), (1, 97), (97, 1), (9, 65), (37, 53), (129, 255)])
 @pytest.mark.parametrize("policy", ["fcfs", "grid", "static", "alternating"])
 def test_ragged_sizes(m, n, policy):
