@@ -199,9 +199,12 @@ typedef struct mandel_sched {
                                 wavefronts; 1..64, or MANDEL_TILE_PARTS_AUTO: with r
                                 the fewest parts that give at least 24 queue items
                                 per resident wavefront, the largest power of two not
-                                above r, capped at 8 and at tile_h (an image of few
-                                tiles is then not left to a few wavefronts;
-                                first_slot must be 0) [1]; GRID ignores it */
+                                above r, at most 8, halved while a part would hold
+                                fewer than 2^20 pixel-iterations at max_iter (unless
+                                the queue holds at most 2 items per wavefront), at
+                                most tile_h (an image of few tiles is then not left
+                                to a few wavefronts, and cheap parts do not queue on
+                                the head; first_slot must be 0) [1]; GRID ignores it */
     int32_t periodicity;     /* 1: exact periodicity detection (needs check_every 0):
                                 in each deferred block the last 32 states of every
                                 lane are compared bit for bit with the block-start

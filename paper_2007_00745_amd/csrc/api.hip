@@ -267,22 +267,35 @@ int test_mode(const mandel_sched &s)
 }
 
 // Launch geometry for a tile policy: persistent groups or one group per tile.
-// MANDEL_TILE_PARTS_AUTO: r = the fewest row parts per tile that give at least
-// AUTO_ITEMS_PER_WAVE queue items per resident wavefront; the parts are the largest power
-// of two not above r (parts of equal height in a tile of 8 rows), at most 8 and at most
-// the tile's rows.  Measured on single views with 64 x 8 tiles (FCFS) over 7168
-// wavefronts: 2048^2 views (8192 tiles) took 4.4-4.7 ms in one part and 2.4-2.5 ms in 8;
-// the 4096^2 full view 9.1-9.2 ms in one part, 7.5-7.6 in 4, 7.9 in 6 and 7.8-7.9 in 8;
-// the 8192^2 one 26.5-26.7 ms in one part, 25.5-25.9 in 2 and 30.4-30.6 in 8, where a
-// million claims queue on the head.
+// MANDEL_TILE_PARTS_AUTO.  Row parts let several wavefronts share one expensive tile, so
+// an image of few tiles per wavefront does not end on a few tiles claimed late; but
+// every part is a claim on the one queue head, and claims of cheap parts queue there.
+// r = the fewest parts that give AUTO_ITEMS_PER_WAVE queue items per resident wavefront;
+// the parts are the largest power of two not above r (parts of equal height in a tile of
+// 8 rows), at most 8; then halved while a part would hold fewer than AUTO_MIN_PART_WORK
+// pixel-iterations at max_iter, unless the whole queue is at most 2 items per
+// wavefront; at most the tile's rows.  Measured on single views with 64 x 8 tiles
+// (FCFS) over 7168 wavefronts, medians of 7 on several boxes: a 2048^2 full view (8192
+// tiles) 4.5-4.7 ms in one part, 2.6 in 4, 2.5 in 8; the 4096^2 one 9.1-9.4 ms in one
+// part, 7.5-7.8 in 4, 7.8-8.2 in 8; the 8192^2 one 26.5-27.3 ms in one part, 25.5-26.8
+// in 2, 30.3-31.1 in 8 (10^6 claims queue on the head); but at max_iter 200 the 8192^2
+// view takes 1.8 ms in one part and 3.3 in 2, and the 8000^2 view at max_iter 2000
+// 6.0-6.2 ms in one part and 6.5-6.6 in 2.
 constexpr int64_t AUTO_ITEMS_PER_WAVE = 24;
+constexpr int64_t AUTO_MIN_PART_WORK = (int64_t)1 << 20;
 
-int32_t auto_tile_parts(int64_t ntiles, int64_t waves, int32_t tile_h)
+int32_t auto_tile_parts(int64_t ntiles, int64_t waves, int32_t tile_w, int32_t tile_h,
+                        int32_t max_iter)
 {
-    const int64_t r = ntiles > 0 ? (AUTO_ITEMS_PER_WAVE * waves + ntiles - 1) / ntiles : 1;
+    if (ntiles <= 0)
+        return 1;
+    const int64_t r = (AUTO_ITEMS_PER_WAVE * waves + ntiles - 1) / ntiles;
     int64_t parts = 1;
     while (parts * 2 <= r && parts < 8)
         parts *= 2;
+    const int64_t tile_work = (int64_t)tile_w * tile_h * max_iter;
+    while (parts > 1 && ntiles * parts > 2 * waves && tile_work / parts < AUTO_MIN_PART_WORK)
+        parts /= 2;
     return (int32_t)(parts < tile_h ? parts : tile_h);
 }
 
@@ -410,7 +423,7 @@ static int render_sched(const mandel_window *w, int32_t m, int32_t n, int32_t ma
             return rc;
         if (s.tile_parts == MANDEL_TILE_PARTS_AUTO)
             a.parts = auto_tile_parts(ntiles, (int64_t)grid.x * grid.y * (block.x / 64),
-                                      s.tile_h);
+                                      s.tile_w, s.tile_h, max_iter);
     }
     hipError_t e = launch_clear(head, s.first_slot, a.tile_cost, a.claims, a.tile_time,
                                 a.tile_cost || a.claims || a.tile_time ? ntiles : 0, a.stats,

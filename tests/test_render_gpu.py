@@ -117,17 +117,19 @@ def test_claims_and_costs(c1_ref):
         assert st[0] * 64 >= st[1]  # lane iterations cannot exceed lane slots
 
 
-@pytest.mark.parametrize("m,n,tw,th,policy", [
-    (480, 640, 64, 8, "fcfs"), (37, 53, 64, 8, "fcfs"), (1, 97, 64, 8, "fcfs"),
-    (1024, 1024, 64, 8, "fcfs"), (1024, 1024, 64, 3, "ordered"), (300, 2000, 16, 16, "fcfs"),
-    (4096, 4096, 64, 8, "fcfs")])
-def test_automatic_row_parts(m, n, tw, th, policy):
+@pytest.mark.parametrize("m,n,tw,th,policy,mi", [
+    (480, 640, 64, 8, "fcfs", 600), (37, 53, 64, 8, "fcfs", 600), (1, 97, 64, 8, "fcfs", 600),
+    (1024, 1024, 64, 8, "fcfs", 600), (1024, 1024, 64, 8, "fcfs", 20000),
+    (1024, 1024, 64, 3, "ordered", 20000), (300, 2000, 16, 16, "fcfs", 3000),
+    (4096, 4096, 64, 8, "fcfs", 600)])
+def test_automatic_row_parts(m, n, tw, th, policy, mi):
     # MANDEL_TILE_PARTS_AUTO: one part count p for the launch, 1 <= p <= min(8, tile_h)
     # (a power of two unless capped by tile_h); every non-empty part of every tile claimed
     # once; counts equal to the oracle's.  With at least 7168 resident wavefronts (the
-    # MI355X's at 7 per SIMD) an image of at most 24 * 7168 / 8 = 21504 tiles gets the cap.
+    # MI355X's at 7 per SIMD) an image of at most 24 * 7168 / 8 = 21504 tiles gets the cap
+    # when its parts still hold 2^20 pixel-iterations at max_iter or the queue is short.
     win = workloads.window_from_bounds(-2.0, 1.0, -1.2, 1.2, m, n)
-    v = workloads.View(win, m, n, 600, 2.0)
+    v = workloads.View(win, m, n, mi, 2.0)
     nt = native.tile_count(m, n, tw, th)
     claims = torch.zeros(nt, dtype=torch.int32, device="cuda")
     kw = dict(policy=policy, tile_w=tw, tile_h=th, tile_parts=native.TILE_PARTS_AUTO,
@@ -135,7 +137,8 @@ def test_automatic_row_parts(m, n, tw, th, policy):
     if policy == "ordered":
         kw["order"] = torch.randperm(nt, device="cuda").to(torch.int32)
     got = gpu_render(v, **kw)
-    want = oracle.render(v.window, m, n, v.max_iter, v.R) if m * n <= 1 << 21 else None
+    want = (oracle.render(v.window, m, n, v.max_iter, v.R)
+            if m * n * mi <= 1 << 28 else None)
     if want is not None:
         assert np.array_equal(got, want)
     else:
@@ -153,8 +156,10 @@ def test_automatic_row_parts(m, n, tw, th, policy):
         if rows:
             assert np.all(c[-1] == sum(1 for q in range(p) if ((q + 1) * rows) // p > (q * rows) // p))
         assert p == cap or p in (1, 2, 4), p
-        if nt * 8 <= 24 * 7168:
+        if nt * 8 <= 24 * 7168 and (nt * 8 <= 2 * 7168 or tw * th * mi // 8 >= 1 << 20):
             assert p == cap, (nt, p)
+        if nt * p > 2 * 8192:
+            assert p == 1 or tw * th * mi // p >= 1 << 20, (nt, p)
     else:
         assert np.all((c >= 1) & (c <= cap))
     _log(f"automatic parts: {nt} tiles -> {p}")
