@@ -202,9 +202,11 @@ typedef struct mandel_sched {
                                 above r, at most 8, halved while a part would hold
                                 fewer than 2^20 pixel-iterations at max_iter (unless
                                 the queue holds at most 2 items per wavefront), at
-                                most tile_h (an image of few tiles is then not left
-                                to a few wavefronts, and cheap parts do not queue on
-                                the head; first_slot must be 0) [1]; GRID ignores it */
+                                most tile_h; 1 when the whole window lies outside
+                                1.03 R (every pixel escapes at once) (an image of few
+                                tiles is then not left to a few wavefronts, and cheap
+                                parts do not queue on the head; first_slot must be 0)
+                                [1]; GRID ignores it */
     int32_t periodicity;     /* 1: exact periodicity detection (needs check_every 0):
                                 in each deferred block the last 32 states of every
                                 lane are compared bit for bit with the block-start

@@ -421,9 +421,18 @@ static int render_sched(const mandel_window *w, int32_t m, int32_t n, int32_t ma
         rc = tile_grid(s, false, ntiles, &grid, &block);
         if (rc)
             return rc;
-        if (s.tile_parts == MANDEL_TILE_PARTS_AUTO)
-            a.parts = auto_tile_parts(ntiles, (int64_t)grid.x * grid.y * (block.x / 64),
-                                      s.tile_w, s.tile_h, max_iter);
+        if (s.tile_parts == MANDEL_TILE_PARTS_AUTO) {
+            // A window whose nearest point to 0 lies well outside the escape radius
+            // escapes at the first test everywhere: its tiles are cheap, keep them whole.
+            const double hx = 0.5 * (double)n * w->dx, hy = 0.5 * (double)m * w->dy;
+            const double nx = std::fmax(0.0, std::fabs(w->cx0) - hx);
+            const double ny = std::fmax(0.0, std::fabs(w->cy0) - hy);
+            const bool outside = nx * nx + ny * ny > 1.0625 * R * R;
+            a.parts = outside ? 1
+                              : auto_tile_parts(ntiles,
+                                                (int64_t)grid.x * grid.y * (block.x / 64),
+                                                s.tile_w, s.tile_h, max_iter);
+        }
     }
     hipError_t e = launch_clear(head, s.first_slot, a.tile_cost, a.claims, a.tile_time,
                                 a.tile_cost || a.claims || a.tile_time ? ntiles : 0, a.stats,

@@ -165,6 +165,16 @@ def test_automatic_row_parts(m, n, tw, th, policy, mi):
     _log(f"automatic parts: {nt} tiles -> {p}")
 
 
+def test_automatic_row_parts_outside_the_radius():
+    # a window entirely outside 1.03 R escapes at the first test everywhere: whole tiles
+    m = n = 1024
+    v = workloads.View((3.0, 3.0, 0.5 / n, 0.5 / m), m, n, 10000, 2.0)
+    nt = native.tile_count(m, n, 64, 8)
+    claims = torch.zeros(nt, dtype=torch.int32, device="cuda")
+    got = gpu_render(v, tile_parts=native.TILE_PARTS_AUTO, claims=claims)
+    assert np.all(got == 1) and np.all(claims.cpu().numpy() == 1)
+
+
 @pytest.mark.parametrize("m,n", [(1, 1), (1, 97), (97, 1), (9, 65), (37, 53), (129, 255)])
 @pytest.mark.parametrize("policy", ["fcfs", "grid", "static", "alternating"])
 def test_ragged_sizes(m, n, policy):
