@@ -29,7 +29,8 @@ CASES = [
 
 
 @pytest.mark.parametrize("sched", [{}, dict(policy="ordered"), dict(check_every=1),
-                                   dict(periodicity=1, block_iters=128)])
+                                   dict(periodicity=1, block_iters=128),
+                                   dict(tile_parts=native.TILE_PARTS_AUTO)])
 def test_noalloc_matches_render_sched_twice(sched):
     # call 1: the larger image; call 2: a smaller one right after, on the same stream,
     # so the second call starts from the first one's leftover head
