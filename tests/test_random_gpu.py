@@ -174,9 +174,14 @@ def test_random_single_view_schedule(seed):
     rows = policy in ("static", "alternating")
     nt = native.tile_count(v.m, v.n, tw, th)
     parts = 1
+    auto = False
     if policy in ("fcfs", "ordered"):
         parts = int(rng.choice([1, 1, 2, 4]))
         kw.update(tile_parts=parts, grain=int(rng.choice([1, 2, 3, 8])))
+        # automatic row parts from a generator of their own (the other draws unchanged)
+        auto = bool(np.random.default_rng(33000 + seed).random() < 0.3)
+        if auto:
+            kw["tile_parts"] = native.TILE_PARTS_AUTO
     if policy == "ordered":
         kw["order"] = torch.tensor(rng.permutation(max(nt, 1)), dtype=torch.int32, device="cuda")
     W = 0
@@ -206,10 +211,19 @@ def test_random_single_view_schedule(seed):
         assert np.array_equal(log, owner)
     else:
         hs = np.minimum(th, v.m - np.arange(0, v.m, th))
-        per = np.array([sum(1 for p in range(parts) if ((p + 1) * h) // parts > (p * h) // parts)
-                        for h in hs])
-        assert np.array_equal(log.reshape(len(hs), -1),
-                              np.repeat(per[:, None], -(-v.n // tw), axis=1))
+
+        def per_tile(parts):
+            per = np.array([sum(1 for p in range(parts) if ((p + 1) * h) // parts > (p * h) // parts)
+                            for h in hs])
+            return np.repeat(per[:, None], -(-v.n // tw), axis=1)
+
+        got_log = log.reshape(len(hs), -1)
+        if auto:
+            # one part count for the launch: a power of two up to 8, or tile_h if smaller
+            cands = sorted({min(p, th) for p in (1, 2, 4, 8)})
+            assert any(np.array_equal(got_log, per_tile(p)) for p in cands), f"seed {seed}"
+        else:
+            assert np.array_equal(got_log, per_tile(parts))
 
 
 @pytest.mark.parametrize("seed", range(24))
