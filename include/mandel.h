@@ -289,7 +289,11 @@ typedef struct mandel_tuning {
     int32_t young_iters;     /* [4] */
     int32_t groups;          /* persistent workgroups [fill the device] */
     int32_t refill_lanes;    /* [16], as in mandel_sched */
-    int32_t tile_parts;      /* [1], as in mandel_sched */
+    int32_t tile_parts;      /* [1], as in mandel_sched; MANDEL_TILE_PARTS_AUTO is
+                                resolved at each launch from its grid, with the
+                                smallest max_iter of the views (1 for row stealing and
+                                the row partitions; launches must then start at
+                                first_slot 0) */
     int32_t collapse_rows;   /* 1: render each distinct row coordinate once.  Where a
                                 view's pitch dy lies below the spacing of doubles near
                                 its centre, neighbouring rows get the same imaginary part

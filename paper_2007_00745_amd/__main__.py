@@ -83,7 +83,9 @@ def main(argv=None) -> int:
         plan = native.Plan([workloads.View((cx, cy, dx, dy), m, n, args.max_iter, args.radius)],
                            {"block_iters": args.block_iters or (128 if args.periodicity
                                                                 else 1024),
-                            "collapse_rows": args.collapse_rows})
+                            "collapse_rows": args.collapse_rows,
+                            # row stealing takes whole tiles; otherwise as mandel_render
+                            "tile_parts": 1 if args.periodicity else native.TILE_PARTS_AUTO})
     torch.cuda.synchronize()  # device, library and plan set-up stay outside the timed part
     t0 = time.perf_counter()
     a.record()

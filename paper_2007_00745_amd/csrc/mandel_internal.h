@@ -20,5 +20,7 @@ int make_view(const mandel_window *w, int32_t m, int32_t n, int32_t max_iter, do
 int check_sched(const mandel_sched *s, mandel_sched *o);
 int tile_grid(const mandel_sched &s, bool batch, int64_t ntiles, dim3 *grid, dim3 *block);
 int test_mode(const mandel_sched &s);
+int32_t auto_tile_parts(int64_t ntiles, int64_t waves, int32_t tile_w, int32_t tile_h,
+                        int32_t max_iter);
 
 } // namespace mandel

@@ -46,6 +46,7 @@ struct mandel_plan {
     int64_t ntiles = 0;
     int64_t npixels = 0;
     int64_t nrows = 0;
+    int32_t min_max_iter = 1 << 30; // smallest max_iter of the views (automatic row parts)
     ViewDesc *d_views = nullptr;
     unsigned long long *d_head = nullptr;
     // buffers of the ordered modes (allocated on first use)
@@ -85,8 +86,6 @@ int fill_tuning(const mandel_tuning *t, mandel_tuning *o)
     std::memset(&d, 0, sizeof d);
     if (t)
         d = *t;
-    if (d.tile_parts == MANDEL_TILE_PARTS_AUTO)
-        return fail(MANDEL_EINVAL, "a plan takes an explicit tile_parts (or the autotuner's)");
     mandel_sched s;
     std::memset(&s, 0, sizeof s);
     s.policy = MANDEL_FCFS_TILES;
@@ -254,7 +253,6 @@ int enqueue(mandel_plan *p, int32_t *out, const mandel_launch &la, hipStream_t s
     a.block_iters = p->tune.block_iters;
     a.young_iters = p->tune.young_iters;
     a.refill_lanes = p->tune.refill_lanes;
-    a.parts = p->tune.tile_parts;
     a.first_slot = la.first_slot;
     a.nrows = p->nrows;
     a.rows = p->d_rows;
@@ -274,6 +272,16 @@ int enqueue(mandel_plan *p, int32_t *out, const mandel_launch &la, hipStream_t s
     int rc = render_grid(p, la, &sc, &grid, &block);
     if (rc)
         return rc;
+    // automatic row parts (single views: as mandel_render chooses them, but without its
+    // test for windows outside the radius; batches with the smallest max_iter of their
+    // views); row stealing takes whole tiles
+    a.parts = p->tune.tile_parts;
+    if (a.parts == MANDEL_TILE_PARTS_AUTO)
+        a.parts = la.steal || rows ? 1
+                                   : auto_tile_parts(p->ntiles,
+                                                     (int64_t)grid.x * grid.y * (block.x / 64),
+                                                     p->tune.tile_w, p->tune.tile_h,
+                                                     p->min_max_iter);
     if (la.steal && (int64_t)grid.x * (block.x / 64) > p->active_len)
         return fail(MANDEL_EINVAL, "held-tile table smaller than the launch");
     e = launch_clear(rows ? nullptr : p->d_head, la.first_slot, la.tile_cost, nullptr,
@@ -366,6 +374,8 @@ int mandel_plan_create(const mandel_view *views, int32_t nviews, const mandel_tu
                     return rc;
                 }
             }
+            if (d.max_iter < p->min_max_iter)
+                p->min_max_iter = d.max_iter;
             d.tile_off = toff;
             d.row_off = p->nrows;
             toff += tile_count(d.m, d.n, tu.tile_w, tu.tile_h);
@@ -470,8 +480,10 @@ int mandel_plan_launch(mandel_plan *p, int32_t *out, const mandel_launch *args, 
         return fail(MANDEL_EINVAL, "steal must be 0 or 1");
     if (la.reserved2 != 0)
         return fail(MANDEL_EINVAL, "reserved2 must be 0");
-    if (la.steal && p->tune.tile_parts != 1)
-        return fail(MANDEL_EINVAL, "row stealing needs tile_parts 1");
+    if (la.steal && p->tune.tile_parts != 1 && p->tune.tile_parts != MANDEL_TILE_PARTS_AUTO)
+        return fail(MANDEL_EINVAL, "row stealing needs tile_parts 1 (or automatic)");
+    if (la.first_slot != 0 && p->tune.tile_parts == MANDEL_TILE_PARTS_AUTO)
+        return fail(MANDEL_EINVAL, "first_slot needs an explicit tile_parts");
     if (la.steal && p->ntiles > INT32_MAX)
         return fail(MANDEL_EINVAL, "row stealing supports at most 2^31 - 1 tiles");
     if (p->ntiles == 0)

@@ -577,3 +577,53 @@ def test_collapsed_rows_refuse_a_resumed_queue():
     torch.cuda.synchronize()
     _check(p, out, [oracle.render(plain[0].window, 480, 640, 1000, 2.0)])
     p.close()
+
+
+@pytest.mark.parametrize("mode,steal", [("fcfs", 0), ("fcfs", 1), ("ordered", 0),
+                                        ("probe", 0), ("learned", 0), ("static", 0),
+                                        ("alternating", 0)])
+def test_plan_automatic_row_parts(mode, steal):
+    # tile_parts = MANDEL_TILE_PARTS_AUTO in a plan, resolved at each launch: counts equal
+    # to the oracle's in every mode, eagerly and from graph replays; in the queue modes
+    # without stealing the launch's work items are the non-empty row parts of every tile
+    # for one part count p (a power of two up to 8); a resumed queue is refused
+    views = [workloads.View(workloads.window_from_bounds(-2.0, 1.0, -1.2, 1.2, 300, 517),
+                            300, 517, 800),
+             workloads.View((-0.7436438870371587, 0.1318259042053119, 2e-7, 2e-7), 133, 201,
+                            3000)]
+    want = [oracle.render(v.window, v.m, v.n, v.max_iter, v.R) for v in views]
+    plan = native.Plan(views, {"tile_parts": native.TILE_PARTS_AUTO})
+    assert plan.tuning["tile_parts"] == native.TILE_PARTS_AUTO
+    kw = {}
+    if mode == "learned":
+        kw["mlp"] = torch.tensor(_params(3), dtype=torch.float32, device="cuda")
+    elif mode == "ordered":
+        kw["order"] = torch.randperm(plan.ntiles, device="cuda").to(torch.int32)
+    elif mode in ("static", "alternating"):
+        kw["workers"] = 29
+    if steal:
+        kw["steal"] = 1
+    out = torch.full((plan.out_size(),), -1, dtype=torch.int32, device="cuda")
+    stats = torch.zeros(8, dtype=torch.int64, device="cuda")
+    for use_graph in (False, True, True):
+        out.fill_(-1)
+        stats.zero_()
+        plan.launch(out, mode=mode, use_graph=use_graph, stats=stats, **kw)
+        torch.cuda.synchronize()
+        _check(plan, out, want)
+        st = stats.cpu().numpy()
+        assert st[1] == sum(int(w.sum(dtype=np.int64)) for w in want)
+        if mode in ("fcfs", "ordered", "probe", "learned") and not steal:
+            def items(p):
+                n = 0
+                for v in views:
+                    hs = np.minimum(8, v.m - np.arange(0, v.m, 8))
+                    per = [sum(1 for q in range(p) if ((q + 1) * h) // p > (q * h) // p)
+                           for h in hs]
+                    n += sum(per) * -(-v.n // 64)
+                return n
+            assert st[3] in {items(p) for p in (1, 2, 4, 8)}, st[3]
+    if mode in ("fcfs", "ordered"):
+        with pytest.raises(native.MandelError):
+            plan.launch(out, mode=mode, first_slot=1, **kw)
+    plan.close()

@@ -167,16 +167,6 @@ def test_empty_image_needs_no_order():
     assert _call(sched=sched) == native.EINVAL   # a real image still needs its order
 
 
-def test_plan_rejects_automatic_row_parts():
-    # plans take an explicit tile_parts (their launches are tuned by the autotuner)
-    v = native.ViewC(native.Window(-0.5, 0.0, 0.01, 0.01), 8, 8, 10, 0, 2.0, 0)
-    arr = (native.ViewC * 1)(v)
-    t = native.Tuning(tile_parts=native.TILE_PARTS_AUTO)
-    h = ctypes.c_void_p()
-    assert native.lib().mandel_plan_create(arr, 1, ctypes.byref(t), ctypes.byref(h)) == native.EINVAL
-    assert b"tile_parts" in native.lib().mandel_last_error()
-
-
 def test_plan_rejects_bad_collapse_flag():
     v = native.ViewC(native.Window(-0.5, 0.0, 0.01, 0.01), 8, 8, 10, 0, 2.0, 0)
     arr = (native.ViewC * 1)(v)
